@@ -1,0 +1,146 @@
+"""Gradients with respect to (log ell, log s, log sigma2) (oracle).
+
+Not in the paper: the hyperparameter adjoint of the approximation defined in
+``oracle.lowrank`` (with nu = 0). For a scalar objective whose derivative with
+respect to K_tilde is the symmetric matrix G, d/dtheta = tr(G dK_tilde/dtheta).
+
+* log-likelihood: G = 1/2 (alpha alpha^T - K_tilde^{-1}), alpha = K_tilde^{-1} y.
+* solve, with cotangent Abar of X = K_tilde^{-1} A: G = -1/2 (X B^T + B X^T),
+  B = K_tilde^{-1} Abar, and dA = B.
+
+With N = Y W^{-1} Y^T, Y = K_f Omega, W = Omega^T Y, Y' = (dK_f/dlog ell) Omega,
+Phi = F^{-1} (so Y W^{-1} = Q Phi):
+
+    d/dlog ell    = 2 <G Q Phi, Y'> - <Phi^T (Q^T G Q) Phi, Omega^T Y'>
+    d/dlog s      = 2 tr(Q^T G Q C)            (N is proportional to s^2)
+    d/dlog sigma2 = sigma2 tr(G)
+
+with, for the log-likelihood, Q^T K_tilde^{-1} = S^{-1} Q^T, so
+G Q = 1/2 (alpha a^T - Q S^{-1}), Q^T G Q = 1/2 (a a^T - S^{-1}), a = Q^T alpha,
+tr K_tilde^{-1} = (n - d) / sigma2 + tr S^{-1}.
+
+``*_dense`` functions evaluate the same derivatives from the plain definition
+with explicit n x n matrices (small n): dN = Y' W^{-1} Y^T + Y W^{-1} Y'^T -
+Y W^{-1} (Omega^T Y') W^{-1} Y^T.
+
+Pins (tests/test_oracle_grad.py): central finite differences (Richardson
+extrapolated) of the oracle's own forward; the dense product-rule form; the
+closed forms d/dlog s = alpha^T (y - sigma2 alpha) - (n - sigma2 tr K_tilde^{-1})
+and d/dlog sigma2 = sigma2/2 (alpha^T alpha - tr K_tilde^{-1}).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import kernels, lowrank, qr, sketch
+
+
+def _phi(core: dict) -> np.ndarray:
+    d = core["F"].shape[0]
+    return sla.lu_solve(core["lu"], np.eye(d), check_finite=False)
+
+
+def _theta_terms(q, core, omega, yprime, gq, qgq, trace_g, sigma2):
+    phi = _phi(core)
+    e = sketch.omega_t_apply(omega, yprime)
+    d_ell = 2.0 * float(np.sum((gq @ phi) * yprime)) - float(np.sum((phi.T @ qgq @ phi) * e))
+    d_s = 2.0 * float(np.sum(qgq * core["C"]))
+    d_sigma2 = sigma2 * trace_g
+    return np.array([d_ell, d_s, d_sigma2])
+
+
+def grad_loglik(x, kind, ell, s, sigma2, omega, q, core, y, alpha, yprime=None):
+    """Gradient of the approximate log-likelihood (nu = 0)."""
+    q = np.asarray(q, dtype=np.float64)
+    n, d = q.shape
+    alpha = np.asarray(alpha, dtype=np.float64).reshape(-1)
+    if yprime is None:
+        yprime = sketch.sketch(x, kind, ell, s, omega, deriv=True)
+    a = q.T @ alpha
+    s_inv = lowrank.s_solve(core["L"], np.eye(d))
+    gq = 0.5 * (np.outer(alpha, a) - q @ s_inv)
+    qgq = 0.5 * (np.outer(a, a) - s_inv)
+    tr_kinv = (n - d) / sigma2 + float(np.trace(s_inv))
+    trace_g = 0.5 * (float(alpha @ alpha) - tr_kinv)
+    return _theta_terms(q, core, omega, yprime, gq, qgq, trace_g, sigma2)
+
+
+def grad_solve(x, kind, ell, s, sigma2, omega, q, core, xsol, abar, yprime=None):
+    """Gradient of <Abar, K_tilde^{-1} A> (nu = 0). Returns (dtheta, dA)."""
+    q = np.asarray(q, dtype=np.float64)
+    xsol = np.asarray(xsol, dtype=np.float64)
+    b = lowrank.apply(q, core["L"], abar, sigma2)
+    if yprime is None:
+        yprime = sketch.sketch(x, kind, ell, s, omega, deriv=True)
+    qx = q.T @ xsol
+    qb = q.T @ b
+    gq = -0.5 * (xsol @ qb.T + b @ qx.T)
+    qgq = -0.5 * (qx @ qb.T + qb @ qx.T)
+    trace_g = -float(np.sum(xsol * b))
+    return _theta_terms(q, core, omega, yprime, gq, qgq, trace_g, sigma2), b
+
+
+# ---------------------------------------------------------------- dense definitions
+
+def _dense_parts(x, kind, ell, s, sigma2, omega):
+    n = np.asarray(x).shape[0]
+    om = sketch.omega_dense(omega, n)
+    kf = kernels.kernel_matrix(kind, x, x, ell, s)
+    kp = kernels.kernel_matrix_dlogell(kind, x, x, ell, s)
+    y = kf @ om
+    yp = kp @ om
+    w = om.T @ y
+    winv_yt = np.linalg.solve(w, y.T)
+    nmat = y @ winv_yt
+    kt = sigma2 * np.eye(n) + nmat
+    dn_ell = yp @ winv_yt + winv_yt.T @ yp.T - winv_yt.T @ (om.T @ yp) @ winv_yt
+    return kt, nmat, dn_ell
+
+
+def grad_loglik_dense(x, kind, ell, s, sigma2, omega, yv):
+    kt, nmat, dn_ell = _dense_parts(x, kind, ell, s, sigma2, omega)
+    n = kt.shape[0]
+    kinv = np.linalg.inv(kt)
+    alpha = kinv @ np.asarray(yv, dtype=np.float64).reshape(-1)
+    g = 0.5 * (np.outer(alpha, alpha) - kinv)
+    return np.array([np.sum(g * dn_ell), np.sum(g * (2.0 * nmat)), sigma2 * np.trace(g)]), n
+
+
+def grad_solve_dense(x, kind, ell, s, sigma2, omega, a, abar):
+    kt, nmat, dn_ell = _dense_parts(x, kind, ell, s, sigma2, omega)
+    xs = np.linalg.solve(kt, np.asarray(a, dtype=np.float64))
+    b = np.linalg.solve(kt, np.asarray(abar, dtype=np.float64))
+    g = -0.5 * (xs @ b.T + b @ xs.T)
+    return np.array([np.sum(g * dn_ell), np.sum(g * (2.0 * nmat)), sigma2 * np.trace(g)]), b
+
+
+# ---------------------------------------------------------------- forward used by FD
+
+def forward(x, kind, ell, s, sigma2, omega, a, leaf_rows, nu=0.0, k_round=None):
+    """Sketch -> blocked QR -> Woodbury solve. Returns dict(Y, Q, R, core..., X, logdet)."""
+    y = sketch.sketch(x, kind, ell, s, omega, nu=nu, k_round=k_round)
+    q, r = qr.tsqr(y, leaf_rows)
+    out = lowrank.solve(q, r, omega, sigma2, a, nu)
+    out.update({"Y": y, "Q": q, "R": r})
+    return out
+
+
+def loglik_at(theta, x, kind, omega, yv, leaf_rows):
+    """Approximate log-likelihood at theta = (log ell, log s, log sigma2)."""
+    ell, s, sigma2 = np.exp(theta[0]), np.exp(theta[1]), np.exp(theta[2])
+    out = forward(x, kind, ell, s, sigma2, omega, np.asarray(yv).reshape(-1, 1), leaf_rows)
+    return lowrank.loglik(yv, out["X"][:, 0], out["logdet"])
+
+
+def fd_gradient(fun, theta, h=1e-3):
+    """Central differences with one Richardson step (error O(h^4))."""
+    theta = np.asarray(theta, dtype=np.float64)
+    g = np.zeros_like(theta)
+    for k in range(theta.shape[0]):
+        e = np.zeros_like(theta)
+        e[k] = 1.0
+        d1 = (fun(theta + h * e) - fun(theta - h * e)) / (2 * h)
+        d2 = (fun(theta + 0.5 * h * e) - fun(theta - 0.5 * h * e)) / h
+        g[k] = (4.0 * d2 - d1) / 3.0
+    return g
