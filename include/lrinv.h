@@ -1,0 +1,186 @@
+/*
+ * lrinv.h - C ABI of the MI355X randomized low-rank covariance inverse.
+ *
+ * Method (Banerjee, Vogelstein, Dunson, "Parallel inversion of huge covariance
+ * matrices"): for points x_1..x_n and a stationary kernel k, with
+ * K_f[i,j] = k(x_i, x_j) and K = K_f + sigma2 I,
+ *   1. sketch   Y = (K_f + nu I) Omega, Omega n x d random (Sec. 3.1) or the
+ *               structured c R H P with H the Walsh-Hadamard matrix (Def. 1,
+ *               Sec. 3.2); K is evaluated on the fly and never stored;
+ *   2. tsqr     Y = Q R by leaf Householder QR of row blocks and a binary tree
+ *               of QRs of stacked R factors (Sec. 3.3, Eq. 1-4);
+ *   3. solve    the Woodbury-form approximation
+ *               K~ = sigma2 I + Q (C - nu I) Q^T,  C = sym(F^{-1} R^T),
+ *               F = Omega^T Q, applied to A: K~^{-1} A = (A - Q Z)/sigma2 +
+ *               Q S^{-1} Z with Z = Q^T A, S = C + (sigma2 - nu) I = L L^T,
+ *               and log|K~| = (n - d) log sigma2 + 2 sum log L_jj. (The paper
+ *               states the target K^{-1} A, Sec. 1, and the column-space
+ *               projection, Sec. 3.1 and the proof of Thm 5, but not this
+ *               formula; this is the projected-process reading of it.)
+ *   4. backward gradients of the approximate Gaussian log-likelihood, or of
+ *               <Abar, K~^{-1} A>, with respect to (log ell, log s, log sigma2).
+ *
+ * Conventions for every entry point:
+ *   - Matrices are row-major and contiguous unless a leading dimension is given.
+ *   - "device" pointers are HIP device memory; "host" pointers are host memory.
+ *   - The caller owns all memory. The library never allocates or frees; scratch
+ *     space comes from the caller's workspace, sized by lr_*_workspace_bytes.
+ *     The workspace pointer must be 256-byte aligned.
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
+ *     stream). Argument errors are detected on the host BEFORE anything is
+ *     launched and nothing is written then. Numerical breakdown is reported in
+ *     a device int32 `info` (see lr_lowrank_solve).
+ *   - Precision `prec`: LR_PREC_F64 (all float64), LR_PREC_F32 (float32 kernel
+ *     tiles, sketch and leaf QR; float64 tree, d x d core and solves),
+ *     LR_PREC_BF16 (as F32, but the dense-Omega sketch rounds K tiles to
+ *     bfloat16 and runs on bf16 matrix cores with float32 accumulation).
+ *     "real" below means double for F64 and float otherwise.
+ *   - Points X are float32 n x D (1 <= D <= 15) in every precision.
+ *   - Sizes: n >= 1, 1 <= d <= 1024, d <= n, 0 <= m <= 64.
+ */
+#ifndef LRINV_H
+#define LRINV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LR_OK = 0,
+  LR_ERR_ARG = 1,         /* NaN/inf/out-of-range scalar, NULL pointer, unknown enum */
+  LR_ERR_SHAPE = 2,       /* inconsistent or out-of-range sizes */
+  LR_ERR_NOT_POW2 = 3,    /* SRHT Omega with n not a power of two */
+  LR_ERR_WORKSPACE = 4,   /* workspace smaller than required or misaligned */
+  LR_ERR_HIP = 5,         /* a HIP runtime call or kernel launch failed */
+  LR_ERR_UNSUPPORTED = 6  /* valid but unsupported combination */
+} lr_status;
+
+typedef enum { LR_KERNEL_SE = 0, LR_KERNEL_MATERN32 = 1 } lr_kernel;
+typedef enum { LR_OMEGA_SRHT = 0, LR_OMEGA_GAUSS = 1 } lr_omega_kind;
+typedef enum { LR_PREC_F64 = 0, LR_PREC_F32 = 1, LR_PREC_BF16 = 2 } lr_prec;
+
+/* Stationary kernel (Sec. 5.1 forms):
+ *   LR_KERNEL_SE       k(r) = s^2 exp(-r^2 / (2 ell^2))
+ *   LR_KERNEL_MATERN32 k(r) = s^2 (1 + u) exp(-u),  u = sqrt(3) r / ell
+ * with r = |x_i - x_j| in difference form. Requires ell > 0, s >= 0, finite. */
+typedef struct {
+  int32_t kernel;   /* lr_kernel */
+  int32_t reserved; /* must be 0 */
+  double ell;
+  double s;
+} lr_hyper;
+
+/* Random matrix Omega (n x d).
+ *   LR_OMEGA_SRHT  (Def. 1 with T = Walsh-Hadamard, Sec. 3.2):
+ *       Omega[j,k] = n^{-1/2} signs[j] (-1)^popcount(j & cols[k]).
+ *       signs: device int8[n] (negative = -1, otherwise +1);
+ *       cols:  device int32[d], distinct, in [0, n) (see lr_check_srht_cols).
+ *       n must be a power of two.
+ *   LR_OMEGA_GAUSS (dense, e.g. i.i.d. N(0, 1/d), Sec. 3.1):
+ *       dense_t: device, Omega TRANSPOSED, d rows of length >= n with leading
+ *       dimension ld (elements, ld >= n, ld % 8 == 0, 16-byte aligned base),
+ *       element type double (F64), float (F32) or bfloat16 bits (BF16). */
+typedef struct {
+  int32_t kind;        /* lr_omega_kind */
+  int32_t d;
+  int64_t n;
+  int64_t ld;          /* GAUSS only */
+  const int8_t *signs; /* SRHT only */
+  const int32_t *cols; /* SRHT only */
+  const void *dense_t; /* GAUSS only */
+} lr_omega;
+
+/* Host-side check of SRHT column indices (host pointer): LR_OK when the d entries
+ * are distinct and in [0, n), LR_ERR_ARG otherwise. Device kernels are memory-safe
+ * for any index values, but the method needs distinct columns. */
+lr_status lr_check_srht_cols(const int32_t *cols_host, int32_t d, int64_t n);
+
+/* ---------------------------------------------------------------- sketch
+ * Y = (K_f + nu I) Omega (Sec. 3.1-3.2), K_f evaluated tile by tile from X and
+ * never written to memory.
+ *   X       device float32 n x D points.
+ *   hyp     host pointer to the kernel description.
+ *   omega   host pointer to the Omega description (omega->n == n).
+ *   nu      shift of the sketched matrix (0 sketches K_f).
+ *   Y       device real n x d output (may be NULL when only Yprime is wanted).
+ *   Yprime  device real n x d output of (dK_f / dlog ell) Omega, or NULL. With
+ *           SRHT and F32 both outputs come from one fused pass.
+ * Unsupported: BF16 with SRHT. */
+size_t lr_sketch_workspace_bytes(int64_t n, int32_t D, int32_t d, int32_t prec);
+lr_status lr_sketch(void *stream, int64_t n, int32_t D, const float *X, const lr_hyper *hyp,
+                    const lr_omega *omega, double nu, int32_t prec, void *Y, void *Yprime,
+                    void *ws, size_t ws_bytes);
+
+/* ---------------------------------------------------------------- tsqr
+ * Binary-tree blocked QR of the n x d matrix Y (Sec. 3.3, Eq. 1-4).
+ *   Rows are split into leaves of leaf_rows rows (the last leaf may be shorter
+ *   but needs >= d rows; d <= leaf_rows <= 8192). Each leaf is factored by
+ *   blocked Householder QR in "real" precision; the leaf R factors are merged
+ *   pairwise (left to right, an unpaired last one is carried up) in float64.
+ *   Y   device real n x d input (not modified).
+ *   Q   device real n x d output with Q^T Q = I.
+ *   R   device double d x d output, upper triangular with diag(R) >= 0 (zeros
+ *       are written below the diagonal); Y = Q R. */
+size_t lr_tsqr_workspace_bytes(int64_t n, int32_t d, int32_t leaf_rows, int32_t prec);
+lr_status lr_tsqr(void *stream, int64_t n, int32_t d, int32_t leaf_rows, int32_t prec,
+                  const void *Y, void *Q, double *R, void *ws, size_t ws_bytes);
+
+/* ---------------------------------------------------------------- lowrank_solve
+ * X = K~^{-1} A and log|K~| from the sketch factors (see the header comment).
+ *   Q, R        outputs of lr_tsqr for the same Omega and nu.
+ *   A, X        device real n x m (X may not alias A); m = 0 computes only the
+ *               factors and log-determinant.
+ *   C           device double d x d: sym(F^{-1} R^T).
+ *   L           device double d x d: lower Cholesky factor of S (upper part 0).
+ *   Flu, piv    device double d x d LU factors of F (unit lower L and U packed,
+ *               LAPACK getrf layout, row-major) and int32[d] pivot rows.
+ *   logdet      device double[1].
+ *   info        device int32[1]: 0 = success; k > 0: the k-th leading minor
+ *               of S is not positive (X is then not written, logdet is NaN);
+ *               k < 0: F has a zero pivot at step -k. logdet is NaN then.
+ *   sigma2 > 0; nu >= 0. */
+size_t lr_lowrank_solve_workspace_bytes(int64_t n, int32_t d, int32_t m, int32_t prec);
+lr_status lr_lowrank_solve(void *stream, int64_t n, int32_t d, int32_t m, const lr_omega *omega,
+                           int32_t prec, const void *Q, const double *R, double sigma2, double nu,
+                           const void *A, void *X, double *C, double *L, double *Flu,
+                           int32_t *piv, double *logdet, int32_t *info, void *ws, size_t ws_bytes);
+
+/* ---------------------------------------------------------------- log-likelihood
+ * out[0] = -1/2 y^T alpha - 1/2 logdet[0] (the approximate Gaussian
+ * log-likelihood without the -n/2 log(2 pi) constant; Sec. 1 names Gaussian
+ * likelihoods as the target use). y, alpha: device real[n]; logdet, out:
+ * device double[1]. Writes NaN when info[0] != 0 (info may be NULL). */
+lr_status lr_loglik(void *stream, int64_t n, int32_t prec, const void *y, const void *alpha,
+                    const double *logdet, const int32_t *info, double *out);
+
+/* ---------------------------------------------------------------- backward
+ * Gradient with respect to theta = (log ell, log s, log sigma2), nu = 0 only.
+ *   mode 0 (log-likelihood -1/2 y^T K~^{-1} y - 1/2 log|K~|): U = alpha = K~^{-1} y
+ *          (device real n x 1, m must be 1), V unused, dA unused.
+ *   mode 1 (solve, cotangent Abar of X = K~^{-1} A): U = X (n x m), V = Abar
+ *          (n x m); dA (device real n x m, or NULL) receives K~^{-1} Abar.
+ *   Q, C, L, Flu, piv   forward factors from lr_tsqr / lr_lowrank_solve.
+ *   Yprime  device real n x d (dK_f/dlog ell) Omega from lr_sketch, or NULL to
+ *           recompute it here (K tiles are recomputed, never stored).
+ *   dtheta  device double[3]. */
+size_t lr_backward_workspace_bytes(int64_t n, int32_t D, int32_t d, int32_t m, int32_t prec);
+lr_status lr_backward(void *stream, int64_t n, int32_t D, const float *X, const lr_hyper *hyp,
+                      const lr_omega *omega, int32_t prec, const void *Q, const double *C,
+                      const double *L, const double *Flu, const int32_t *piv, double sigma2,
+                      int32_t mode, int32_t m, const void *U, const void *V, const void *Yprime,
+                      double *dtheta, void *dA, void *ws, size_t ws_bytes);
+
+/* Human-readable status name (static string). */
+const char *lr_status_string(int32_t status);
+
+/* ABI version: (major << 16) | minor. */
+int32_t lr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LRINV_H */

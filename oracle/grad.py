@@ -41,17 +41,25 @@ def _phi(core: dict) -> np.ndarray:
     return sla.lu_solve(core["lu"], np.eye(d), check_finite=False)
 
 
-def _theta_terms(q, core, omega, yprime, gq, qgq, trace_g, sigma2):
+def _theta_terms(q, core, omega, yprime, gq, qgq, trace_g, sigma2, trace_scale):
     phi = _phi(core)
     e = sketch.omega_t_apply(omega, yprime)
-    d_ell = 2.0 * float(np.sum((gq @ phi) * yprime)) - float(np.sum((phi.T @ qgq @ phi) * e))
+    t1 = 2.0 * float(np.sum((gq @ phi) * yprime))
+    t2 = float(np.sum((phi.T @ qgq @ phi) * e))
     d_s = 2.0 * float(np.sum(qgq * core["C"]))
-    d_sigma2 = sigma2 * trace_g
-    return np.array([d_ell, d_s, d_sigma2])
+    grad = np.array([t1 - t2, d_s, sigma2 * trace_g])
+    # magnitude of what each component sums (for rounding-error scales in tests)
+    scale = np.array([abs(t1) + abs(t2), 2.0 * float(np.sum(np.abs(qgq * core["C"]))), sigma2 * trace_scale])
+    return grad, scale
 
 
-def grad_loglik(x, kind, ell, s, sigma2, omega, q, core, y, alpha, yprime=None):
-    """Gradient of the approximate log-likelihood (nu = 0)."""
+def grad_loglik(x, kind, ell, s, sigma2, omega, q, core, y, alpha, yprime=None, parts=False):
+    """Gradient of the approximate log-likelihood (nu = 0).
+
+    With ``parts`` also returns, per component, the sum of the magnitudes of the
+    terms it adds up (|T1| + |T2| for log ell; for log s and log sigma2 the terms
+    of their closed forms, alpha^T y, sigma2 alpha^T alpha, n, sigma2 tr K~^{-1}).
+    """
     q = np.asarray(q, dtype=np.float64)
     n, d = q.shape
     alpha = np.asarray(alpha, dtype=np.float64).reshape(-1)
@@ -62,12 +70,17 @@ def grad_loglik(x, kind, ell, s, sigma2, omega, q, core, y, alpha, yprime=None):
     gq = 0.5 * (np.outer(alpha, a) - q @ s_inv)
     qgq = 0.5 * (np.outer(a, a) - s_inv)
     tr_kinv = (n - d) / sigma2 + float(np.trace(s_inv))
-    trace_g = 0.5 * (float(alpha @ alpha) - tr_kinv)
-    return _theta_terms(q, core, omega, yprime, gq, qgq, trace_g, sigma2)
+    aa = float(alpha @ alpha)
+    trace_g = 0.5 * (aa - tr_kinv)
+    g, scale = _theta_terms(q, core, omega, yprime, gq, qgq, trace_g, sigma2, 0.5 * (aa + tr_kinv))
+    ya = abs(float(np.asarray(y, dtype=np.float64).reshape(-1) @ alpha))
+    scale[1] = ya + sigma2 * aa + n + sigma2 * tr_kinv
+    return (g, scale) if parts else g
 
 
-def grad_solve(x, kind, ell, s, sigma2, omega, q, core, xsol, abar, yprime=None):
-    """Gradient of <Abar, K_tilde^{-1} A> (nu = 0). Returns (dtheta, dA)."""
+def grad_solve(x, kind, ell, s, sigma2, omega, q, core, xsol, abar, yprime=None, parts=False):
+    """Gradient of <Abar, K_tilde^{-1} A> (nu = 0). Returns (dtheta, dA), or
+    (dtheta, dA, scale) with ``parts`` (scale as in grad_loglik)."""
     q = np.asarray(q, dtype=np.float64)
     xsol = np.asarray(xsol, dtype=np.float64)
     b = lowrank.apply(q, core["L"], abar, sigma2)
@@ -78,7 +91,8 @@ def grad_solve(x, kind, ell, s, sigma2, omega, q, core, xsol, abar, yprime=None)
     gq = -0.5 * (xsol @ qb.T + b @ qx.T)
     qgq = -0.5 * (qx @ qb.T + qb @ qx.T)
     trace_g = -float(np.sum(xsol * b))
-    return _theta_terms(q, core, omega, yprime, gq, qgq, trace_g, sigma2), b
+    g, scale = _theta_terms(q, core, omega, yprime, gq, qgq, trace_g, sigma2, float(np.sum(np.abs(xsol * b))))
+    return (g, b, scale) if parts else (g, b)
 
 
 # ---------------------------------------------------------------- dense definitions

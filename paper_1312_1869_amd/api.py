@@ -1,0 +1,209 @@
+"""Torch-facing wrappers of the lrinv C ABI.
+
+Tensors supply device memory and the current stream; every step of the method
+runs in liblrinv.so. Functions mirror the C entry points:
+
+* ``sketch``        Y = (K_f + nu I) Omega           (lr_sketch)
+* ``tsqr``          Y = Q R, binary-tree blocked QR  (lr_tsqr)
+* ``lowrank_solve`` K~^{-1} A, log|K~|, factors      (lr_lowrank_solve)
+* ``loglik``        -1/2 y^T alpha - 1/2 log|K~|      (lr_loglik)
+* ``backward``      d/d(log ell, log s, log sigma2)  (lr_backward)
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def real_dtype(prec: str) -> torch.dtype:
+    return torch.float64 if prec == "f64" else torch.float32
+
+
+def _p(t) -> ctypes.c_void_p | None:
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device: torch.device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class _Workspace:
+    """A 256-byte aligned device scratch buffer kept alive by the caller."""
+
+    def __init__(self, nbytes: int, device: torch.device):
+        self.nbytes = int(nbytes)
+        self.buf = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device) if nbytes > 0 else None
+        if self.buf is None:
+            self.ptr = None
+        else:
+            addr = self.buf.data_ptr()
+            self.ptr = ctypes.c_void_p((addr + 255) & ~255)
+
+
+@dataclasses.dataclass
+class Hyper:
+    kernel: str
+    ell: float
+    s: float
+
+    def struct(self) -> L.LrHyper:
+        return L.LrHyper(L.KERNELS[self.kernel], 0, float(self.ell), float(self.s))
+
+
+@dataclasses.dataclass
+class Omega:
+    kind: str
+    n: int
+    d: int
+    signs: torch.Tensor | None = None
+    cols: torch.Tensor | None = None
+    dense_t: torch.Tensor | None = None
+    ld: int = 0
+
+    @staticmethod
+    def srht(signs: np.ndarray, cols: np.ndarray, device) -> "Omega":
+        cols = np.ascontiguousarray(cols, dtype=np.int32)
+        n = int(signs.shape[0])
+        L.check(L.lib().lr_check_srht_cols(cols.ctypes.data_as(ctypes.c_void_p), int(cols.shape[0]), n),
+                "lr_check_srht_cols")
+        return Omega("srht", n, int(cols.shape[0]),
+                     signs=torch.from_numpy(np.ascontiguousarray(signs, dtype=np.int8)).to(device),
+                     cols=torch.from_numpy(cols).to(device))
+
+    @staticmethod
+    def gauss(omega_t: np.ndarray, prec: str, device) -> "Omega":
+        """Omega given transposed (d x n); stored d x ld with ld = n rounded up to 64."""
+        d, n = omega_t.shape
+        ld = (n + 63) // 64 * 64
+        dt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[prec]
+        host = torch.zeros((d, ld), dtype=torch.float32)
+        host[:, :n] = torch.from_numpy(np.ascontiguousarray(omega_t, dtype=np.float32))
+        if prec == "f64":
+            host = host.to(torch.float64)
+        return Omega("gauss", n, d, dense_t=host.to(dt).to(device), ld=ld)
+
+    def struct(self) -> L.LrOmega:
+        if self.kind == "srht":
+            return L.LrOmega(L.LR_OMEGA_SRHT, self.d, self.n, 0, _p(self.signs), _p(self.cols), None)
+        return L.LrOmega(L.LR_OMEGA_GAUSS, self.d, self.n, self.ld, None, None, _p(self.dense_t))
+
+
+def _check_real(t: torch.Tensor, prec: str, name: str) -> None:
+    if t.dtype != real_dtype(prec) or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError(f"{name} must be a contiguous CUDA {real_dtype(prec)} tensor")
+
+
+def sketch(X: torch.Tensor, hyper: Hyper, omega: Omega, prec: str, nu: float = 0.0, want_y: bool = True,
+           want_yprime: bool = False):
+    if X.dtype != torch.float32 or not X.is_contiguous():
+        raise ValueError("points must be contiguous float32")
+    n, D = X.shape
+    dev = X.device
+    rd = real_dtype(prec)
+    Y = torch.empty((n, omega.d), dtype=rd, device=dev) if want_y else None
+    Yp = torch.empty((n, omega.d), dtype=rd, device=dev) if want_yprime else None
+    lib = L.lib()
+    ws = _Workspace(lib.lr_sketch_workspace_bytes(n, D, omega.d, L.PRECS[prec]), dev)
+    h, o = hyper.struct(), omega.struct()
+    L.check(lib.lr_sketch(_stream(dev), n, D, _p(X), ctypes.byref(h), ctypes.byref(o), float(nu), L.PRECS[prec],
+                          _p(Y), _p(Yp), ws.ptr, ws.nbytes), "lr_sketch")
+    return Y, Yp
+
+
+def tsqr(Y: torch.Tensor, leaf_rows: int, prec: str):
+    _check_real(Y, prec, "Y")
+    n, d = Y.shape
+    dev = Y.device
+    Q = torch.empty_like(Y)
+    R = torch.empty((d, d), dtype=torch.float64, device=dev)
+    lib = L.lib()
+    ws = _Workspace(lib.lr_tsqr_workspace_bytes(n, d, leaf_rows, L.PRECS[prec]), dev)
+    L.check(lib.lr_tsqr(_stream(dev), n, d, int(leaf_rows), L.PRECS[prec], _p(Y), _p(Q), _p(R), ws.ptr, ws.nbytes),
+            "lr_tsqr")
+    return Q, R
+
+
+@dataclasses.dataclass
+class SolveOut:
+    X: torch.Tensor | None
+    C: torch.Tensor
+    L: torch.Tensor
+    Flu: torch.Tensor
+    piv: torch.Tensor
+    logdet: torch.Tensor
+    info: torch.Tensor
+
+
+def lowrank_solve(Q: torch.Tensor, R: torch.Tensor, omega: Omega, prec: str, sigma2: float,
+                  A: torch.Tensor | None, nu: float = 0.0) -> SolveOut:
+    _check_real(Q, prec, "Q")
+    n, d = Q.shape
+    dev = Q.device
+    m = 0 if A is None else int(A.shape[1])
+    if A is not None:
+        _check_real(A, prec, "A")
+    X = torch.empty_like(A) if A is not None else None
+    f64 = dict(dtype=torch.float64, device=dev)
+    out = SolveOut(X, torch.empty((d, d), **f64), torch.empty((d, d), **f64), torch.empty((d, d), **f64),
+                   torch.empty(d, dtype=torch.int32, device=dev), torch.empty(1, **f64),
+                   torch.empty(1, dtype=torch.int32, device=dev))
+    lib = L.lib()
+    ws = _Workspace(lib.lr_lowrank_solve_workspace_bytes(n, d, m, L.PRECS[prec]), dev)
+    o = omega.struct()
+    L.check(lib.lr_lowrank_solve(_stream(dev), n, d, m, ctypes.byref(o), L.PRECS[prec], _p(Q), _p(R), float(sigma2),
+                                 float(nu), _p(A), _p(X), _p(out.C), _p(out.L), _p(out.Flu), _p(out.piv),
+                                 _p(out.logdet), _p(out.info), ws.ptr, ws.nbytes), "lr_lowrank_solve")
+    return out
+
+
+def loglik(y: torch.Tensor, alpha: torch.Tensor, logdet: torch.Tensor, info: torch.Tensor | None,
+           prec: str) -> torch.Tensor:
+    out = torch.empty(1, dtype=torch.float64, device=y.device)
+    L.check(L.lib().lr_loglik(_stream(y.device), int(y.numel()), L.PRECS[prec], _p(y), _p(alpha), _p(logdet),
+                              _p(info), _p(out)), "lr_loglik")
+    return out
+
+
+def backward(X: torch.Tensor, hyper: Hyper, omega: Omega, prec: str, fac: SolveOut, Q: torch.Tensor, sigma2: float,
+             mode: int, U: torch.Tensor, V: torch.Tensor | None = None, Yprime: torch.Tensor | None = None,
+             want_dA: bool = False):
+    n, D = X.shape
+    dev = X.device
+    m = int(U.shape[1]) if U.dim() == 2 else 1
+    dtheta = torch.empty(3, dtype=torch.float64, device=dev)
+    dA = torch.empty_like(V) if (want_dA and V is not None) else None
+    lib = L.lib()
+    ws = _Workspace(lib.lr_backward_workspace_bytes(n, D, omega.d, m, L.PRECS[prec]), dev)
+    h, o = hyper.struct(), omega.struct()
+    L.check(lib.lr_backward(_stream(dev), n, D, _p(X), ctypes.byref(h), ctypes.byref(o), L.PRECS[prec], _p(Q),
+                            _p(fac.C), _p(fac.L), _p(fac.Flu), _p(fac.piv), float(sigma2), int(mode), m, _p(U), _p(V),
+                            _p(Yprime), _p(dtheta), _p(dA), ws.ptr, ws.nbytes), "lr_backward")
+    return dtheta, dA
+
+
+@dataclasses.dataclass
+class Forward:
+    Y: torch.Tensor
+    Yprime: torch.Tensor | None
+    Q: torch.Tensor
+    R: torch.Tensor
+    sol: SolveOut
+
+
+def forward(X: torch.Tensor, hyper: Hyper, omega: Omega, prec: str, sigma2: float, A: torch.Tensor | None,
+            leaf_rows: int, nu: float = 0.0, want_yprime: bool = False) -> Forward:
+    """Sketch -> blocked QR -> Woodbury solve, all on the current stream."""
+    Y, Yp = sketch(X, hyper, omega, prec, nu=nu, want_yprime=want_yprime)
+    Q, R = tsqr(Y, leaf_rows, prec)
+    sol = lowrank_solve(Q, R, omega, prec, sigma2, A, nu=nu)
+    return Forward(Y, Yp, Q, R, sol)
+
+
+def theta_of(hyper: Hyper, sigma2: float):
+    return (math.log(hyper.ell), math.log(hyper.s), math.log(sigma2))

@@ -1,0 +1,573 @@
+// Binary-tree blocked QR of a tall matrix (Sec. 3.3, Eq. 1-4).
+//
+// One batched blocked-Householder engine serves every level:
+//   * leaves (Eq. 1): each row block of Y, in the working precision T;
+//   * tree nodes (Eq. 2-3): the stacked pair [R_a; R_b] of child R factors,
+//     always in float64;
+//   * Q formation (Eq. 4): Q = blockdiag(leaf Q) (tree Q) [I; 0] is built top
+//     down: every node maps its d x d block M to Q_node [M; 0], whose halves are
+//     the children's blocks, and every leaf writes its rows Q_leaf [M_leaf; 0].
+// A panel of NB columns is factored by one 1024-thread workgroup per matrix
+// (rows in registers, one block reduction per reflector), producing LAPACK
+// style reflectors (beta = -sign(alpha) |x|, tau = 0 when the part below the
+// diagonal is zero) and the compact-WY factor T with H_1 ... H_NB = I - V T V^T.
+// The trailing columns and Q formation are rank-NB updates B -= V (T' (V^T B))
+// spread over (column block x matrix) workgroups.
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace lr {
+
+constexpr int kPanelThreads = 1024;
+constexpr int kPanelWaves = kPanelThreads / 64;
+constexpr int kUpdThreads = 256;
+constexpr int kUpdCols = 64;
+
+template <typename T, int NV>
+__device__ __forceinline__ void block_sum_vec(T (&v)[NV], int nvalid, T* red, T* res) {
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < NV; ++i)
+    if (i < nvalid) v[i] = wave_sum(v[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+      if (i < nvalid) red[w * NV + i] = v[i];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nvalid) {
+    T s = 0;
+    for (int k = 0; k < kPanelWaves; ++k) s += red[k * NV + threadIdx.x];
+    res[threadIdx.x] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i)
+    if (i < nvalid) v[i] = res[i];
+}
+
+// Factor columns [p0, p0 + nbw) of every matrix in the batch (rows p0 .. m-1).
+template <typename T, int RPT, int NB>
+__global__ __launch_bounds__(kPanelThreads) void panel_factor_kernel(T* __restrict__ A, int64_t bstride, int m_full,
+                                                                     int m_last, int nbatch, int ld, int p0, int nbw,
+                                                                     T* __restrict__ tau_all, int64_t tau_bstride,
+                                                                     T* __restrict__ tmat, int64_t t_bstride) {
+  __shared__ T red[kPanelWaves * NB];
+  __shared__ T res[NB];
+  __shared__ T s_alpha;
+  __shared__ T s_tau[NB];
+  __shared__ T s_y[NB * NB];  // s_y[c * NB + c1] = (V^T v_c)[c1], c1 < c
+
+  const int b = blockIdx.x;
+  const int m = (b == nbatch - 1) ? m_last : m_full;
+  T* M = A + (int64_t)b * bstride;
+  const int rows = m - p0;
+  const int t = threadIdx.x;
+
+  T a[RPT][NB];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int lr = t + k * kPanelThreads;
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      a[k][c] = (lr < rows && c < nbw) ? M[(int64_t)(p0 + lr) * ld + p0 + c] : (T)0;
+  }
+
+  for (int c = 0; c < nbw; ++c) {
+    // sigma = |x below the diagonal|^2 ; alpha = diagonal entry
+    T part[1] = {0};
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int lr = t + k * kPanelThreads;
+      if (lr > c && lr < rows) part[0] += a[k][c] * a[k][c];
+    }
+    if (t == c) s_alpha = a[0][c];
+    block_sum_vec<T, 1>(part, 1, red, res);
+    const T sigma = part[0];
+    const T alpha = s_alpha;
+    T tau, beta, scal;
+    if (sigma == (T)0) {
+      tau = 0;
+      beta = alpha;
+      scal = 0;
+    } else {
+      const T nrm = sqrt(alpha * alpha + sigma);
+      beta = alpha >= (T)0 ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      scal = (T)1 / (alpha - beta);
+    }
+    // reflector v (unit at the diagonal), R diagonal entry
+    T vk[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int lr = t + k * kPanelThreads;
+      if (lr > c && lr < rows) {
+        a[k][c] *= scal;
+        vk[k] = a[k][c];
+      } else {
+        vk[k] = (lr == c) ? (T)1 : (T)0;
+      }
+      if (lr == c) a[k][c] = beta;
+    }
+    // w[c'] = v^T x_{c'} for c' > c ; y[c1] = v_{c1}^T v for c1 < c
+    T wv[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) wv[i] = 0;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int lr = t + k * kPanelThreads;
+      if (lr < rows && lr >= c) {
+        // i > c: a[k][i] is x_i(lr); i < c: a[k][i] is the stored reflector
+        // entry v_i(lr) (lr >= c > i), so both sums are v^T a[:, i].
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+          if (i != c) wv[i] += vk[k] * a[k][i];
+      }
+    }
+    block_sum_vec<T, NB>(wv, nbw, red, res);
+    if (t == 0) {
+      s_tau[c] = tau;
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        if (i < c) s_y[c * NB + i] = wv[i];
+    }
+    // apply H = I - tau v v^T to the remaining panel columns
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        if (i > c && i < nbw) a[k][i] -= tau * wv[i] * vk[k];
+    }
+  }
+  __syncthreads();
+
+  // write the panel back (R on/above the diagonal, V below)
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int lr = t + k * kPanelThreads;
+    if (lr < rows) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c < nbw) M[(int64_t)(p0 + lr) * ld + p0 + c] = a[k][c];
+    }
+  }
+  if (t == 0) {
+    T* tau_b = tau_all + (int64_t)b * tau_bstride;
+    for (int c = 0; c < nbw; ++c) tau_b[p0 + c] = s_tau[c];
+    // T: upper triangular, T[c][c] = tau_c, T[0:c, c] = -tau_c T[0:c, 0:c] y_c
+    T* Tm = tmat + (int64_t)b * t_bstride;
+    for (int i = 0; i < NB * NB; ++i) Tm[i] = 0;
+    for (int c = 0; c < nbw; ++c) {
+      const T tc = s_tau[c];
+      for (int r = 0; r < c; ++r) {
+        T s = 0;
+        for (int q = r; q < c; ++q) s += Tm[r * NB + q] * s_y[c * NB + q];
+        Tm[r * NB + c] = -tc * s;
+      }
+      Tm[c * NB + c] = tc;
+    }
+  }
+}
+
+// B[p0:, cols] <- (I - V T' V^T) B[p0:, cols], T' = T^T (TRANS) or T.
+// V occupies columns [p0, p0 + NB) of Vmat (unit diagonal, zeros above).
+template <typename T, int NB, bool TRANS>
+__global__ __launch_bounds__(kUpdThreads) void panel_apply_kernel(const T* Vmat, int64_t vstride, T* Bmat,
+                                                                  int64_t bstride, int m_full, int m_last,
+                                                                  int nbatch, int ld, int p0, int nbw,
+                                                                  int col_begin, int col_end,
+                                                                  const T* __restrict__ tmat, int64_t t_bstride) {
+  __shared__ T red[4][NB][kUpdCols];
+  __shared__ T wsh[NB][kUpdCols];
+  __shared__ T Ts[NB * NB];
+
+  const int b = blockIdx.y;
+  const int m = (b == nbatch - 1) ? m_last : m_full;
+  const T* V = Vmat + (int64_t)b * vstride;
+  T* B = Bmat + (int64_t)b * bstride;
+  const int rows = m - p0;
+  const int t = threadIdx.x;
+  const int cl = t & (kUpdCols - 1);
+  const int rg = wave_uniform(t >> 6);
+  const int col = col_begin + blockIdx.x * kUpdCols + cl;
+  const bool col_ok = col < col_end;
+
+  if (t < NB * NB) Ts[t] = tmat[(int64_t)b * t_bstride + t];
+
+  T acc[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) acc[i] = 0;
+  // rows inside the triangular top of V
+  for (int lr = rg; lr < NB && lr < rows; lr += 4) {
+    const T x = col_ok ? B[(int64_t)(p0 + lr) * ld + col] : (T)0;
+    const T* vr = V + (int64_t)(p0 + lr) * ld + p0;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const T vl = vr[i < nbw ? i : 0];  // index kept inside the panel
+      const T vi = (i < lr && i < nbw) ? vl : (i == lr && i < nbw ? (T)1 : (T)0);
+      acc[i] += vi * x;
+    }
+  }
+  const int lr0 = NB + ((rg - NB % 4 + 4) % 4);
+  for (int lr = lr0; lr < rows; lr += 4) {
+    const T x = col_ok ? B[(int64_t)(p0 + lr) * ld + col] : (T)0;
+    const T* vr = V + (int64_t)(p0 + lr) * ld + p0;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const T vl = vr[i < nbw ? i : 0];
+      const T vi = (i < nbw) ? vl : (T)0;
+      acc[i] += vi * x;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i) red[rg][i][cl] = acc[i];
+  __syncthreads();
+  if (t < kUpdCols) {
+    T w[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) w[i] = red[0][i][t] + red[1][i][t] + red[2][i][t] + red[3][i][t];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      T s = 0;
+      if (TRANS) {
+        // (T^T w)_i = sum_{k <= i} T[k][i] w_k
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+          if (k <= i) s += Ts[k * NB + i] * w[k];
+      } else {
+        // (T w)_i = sum_{k >= i} T[i][k] w_k
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+          if (k >= i) s += Ts[i * NB + k] * w[k];
+      }
+      wsh[i][t] = s;
+    }
+  }
+  __syncthreads();
+  T wl[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) wl[i] = wsh[i][cl];
+  if (!col_ok) return;
+  for (int lr = rg; lr < NB && lr < rows; lr += 4) {
+    const T* vr = V + (int64_t)(p0 + lr) * ld + p0;
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const T vl = vr[i < nbw ? i : 0];
+      const T vi = (i < lr && i < nbw) ? vl : (i == lr && i < nbw ? (T)1 : (T)0);
+      s += vi * wl[i];
+    }
+    B[(int64_t)(p0 + lr) * ld + col] -= s;
+  }
+  for (int lr = lr0; lr < rows; lr += 4) {
+    const T* vr = V + (int64_t)(p0 + lr) * ld + p0;
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const T vl = vr[i < nbw ? i : 0];
+      const T vi = (i < nbw) ? vl : (T)0;
+      s += vi * wl[i];
+    }
+    B[(int64_t)(p0 + lr) * ld + col] -= s;
+  }
+}
+
+// Rdst[b] = upper triangle of the top d x d block of src[b] (as double, zeros below).
+template <typename T>
+__global__ void extract_r_kernel(const T* __restrict__ src, int64_t sstride, int ld, int d,
+                                 double* __restrict__ dst, int nbatch) {
+  const int b = blockIdx.y;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)d * d) return;
+  const int i = (int)(idx / d), j = (int)(idx % d);
+  dst[(int64_t)b * d * d + idx] = (j >= i) ? (double)src[(int64_t)b * sstride + (int64_t)i * ld + j] : 0.0;
+}
+
+// Bdst[b] (rows x d, ld d) = [M[b] (d x d, double); 0].
+template <typename T>
+__global__ void init_qblock_kernel(const double* __restrict__ M, T* __restrict__ dst, int64_t dstride, int m_full,
+                                   int m_last, int nbatch, int d) {
+  const int b = blockIdx.y;
+  const int m = (b == nbatch - 1) ? m_last : m_full;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)m * d) return;
+  const int i = (int)(idx / d);
+  dst[(int64_t)b * dstride + idx] = (i < d) ? (T)M[(int64_t)b * d * d + idx] : (T)0;
+}
+
+// Final R with diag >= 0 and the root block M = diag(sign).
+__global__ void finalize_r_kernel(const double* __restrict__ Rroot, double* __restrict__ R,
+                                  double* __restrict__ Mroot, int d) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)d * d) return;
+  const int i = (int)(idx / d), j = (int)(idx % d);
+  const double sg = Rroot[(int64_t)i * d + i] < 0.0 ? -1.0 : 1.0;
+  R[idx] = (j >= i) ? sg * Rroot[idx] : 0.0;
+  const double sj = Rroot[(int64_t)j * d + j] < 0.0 ? -1.0 : 1.0;
+  Mroot[idx] = (i == j) ? sj : 0.0;
+}
+
+template <typename T>
+__global__ void copy_kernel(const T* __restrict__ src, T* __restrict__ dst, int64_t count) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx < count) dst[idx] = src[idx];
+}
+
+// ------------------------------------------------------------------ host side
+
+static int pick_rpt(int m) {
+  if (m <= 1024) return 1;
+  if (m <= 2048) return 2;
+  if (m <= 4096) return 4;
+  return 8;
+}
+
+// Panel width: keep the register panel at <= 64 VGPRs per thread.
+template <typename T>
+static int pick_nb(int rpt) {
+  const int words = rpt * (int)(sizeof(T) / 4);
+  if (words <= 4) return 16;
+  if (words <= 8) return 8;
+  return 4;
+}
+
+struct QrShape {
+  int m_full, m_last, nbatch, d, nb, npanels;
+};
+
+template <typename T>
+static QrShape qr_shape(int m_full, int m_last, int nbatch, int d) {
+  QrShape s;
+  s.m_full = m_full;
+  s.m_last = m_last;
+  s.nbatch = nbatch;
+  s.d = d;
+  s.nb = pick_nb<T>(pick_rpt(m_full > m_last ? m_full : m_last));
+  s.npanels = (d + s.nb - 1) / s.nb;
+  return s;
+}
+
+template <typename T, int RPT, int NB>
+static hipError_t launch_panel_factor_rn(hipStream_t st, T* A, int64_t bstride, const QrShape& s, int p0, int nbw,
+                                         T* tau, T* tm) {
+  hipLaunchKernelGGL((panel_factor_kernel<T, RPT, NB>), dim3(s.nbatch), dim3(kPanelThreads), 0, st, A, bstride,
+                     s.m_full, s.m_last, s.nbatch, s.d, p0, nbw, tau, (int64_t)s.d, tm,
+                     (int64_t)s.npanels * NB * NB);
+  return hipGetLastError();
+}
+
+template <typename T, int NB>
+static hipError_t launch_panel_factor_nb(hipStream_t st, int rpt, T* A, int64_t bstride, const QrShape& s, int p0,
+                                         int nbw, T* tau, T* tm) {
+  switch (rpt) {
+    case 1: return launch_panel_factor_rn<T, 1, NB>(st, A, bstride, s, p0, nbw, tau, tm);
+    case 2: return launch_panel_factor_rn<T, 2, NB>(st, A, bstride, s, p0, nbw, tau, tm);
+    case 4: return launch_panel_factor_rn<T, 4, NB>(st, A, bstride, s, p0, nbw, tau, tm);
+    default: return launch_panel_factor_rn<T, 8, NB>(st, A, bstride, s, p0, nbw, tau, tm);
+  }
+}
+
+template <typename T, int NB, bool TRANS>
+static hipError_t launch_apply_nb(hipStream_t st, const T* V, int64_t vstride, T* B, int64_t bstride,
+                                  const QrShape& s, int p0, int nbw, int c0, int c1, const T* tm) {
+  if (c1 <= c0) return hipSuccess;
+  const int ncb = (c1 - c0 + kUpdCols - 1) / kUpdCols;
+  hipLaunchKernelGGL((panel_apply_kernel<T, NB, TRANS>), dim3(ncb, s.nbatch), dim3(kUpdThreads), 0, st, V, vstride,
+                     B, bstride, s.m_full, s.m_last, s.nbatch, s.d, p0, nbw, c0, c1, tm,
+                     (int64_t)s.npanels * NB * NB);
+  return hipGetLastError();
+}
+
+template <typename T, bool TRANS>
+static hipError_t launch_apply(hipStream_t st, int nb, const T* V, int64_t vstride, T* B, int64_t bstride,
+                               const QrShape& s, int p0, int nbw, int c0, int c1, const T* tm) {
+  if (nb == 16) return launch_apply_nb<T, 16, TRANS>(st, V, vstride, B, bstride, s, p0, nbw, c0, c1, tm);
+  if (nb == 8) return launch_apply_nb<T, 8, TRANS>(st, V, vstride, B, bstride, s, p0, nbw, c0, c1, tm);
+  return launch_apply_nb<T, 4, TRANS>(st, V, vstride, B, bstride, s, p0, nbw, c0, c1, tm);
+}
+
+#define LR_TRY(x)                          \
+  do {                                     \
+    hipError_t e__ = (x);                  \
+    if (e__ != hipSuccess) return e__;     \
+  } while (0)
+
+// Batched Householder QR in place: A[b] (m_b x d, ld d) -> R (upper) + V (below).
+template <typename T>
+static hipError_t batched_qr(hipStream_t st, T* A, int64_t bstride, const QrShape& s, T* tau, T* tm) {
+  const int rpt = pick_rpt(s.m_full > s.m_last ? s.m_full : s.m_last);
+  for (int p = 0; p < s.npanels; ++p) {
+    const int p0 = p * s.nb;
+    const int nbw = (s.d - p0) < s.nb ? (s.d - p0) : s.nb;
+    T* tmp = tm + (int64_t)p * s.nb * s.nb;
+    if (s.nb == 16) {
+      LR_TRY((launch_panel_factor_nb<T, 16>(st, rpt, A, bstride, s, p0, nbw, tau, tmp)));
+    } else if (s.nb == 8) {
+      LR_TRY((launch_panel_factor_nb<T, 8>(st, rpt, A, bstride, s, p0, nbw, tau, tmp)));
+    } else {
+      LR_TRY((launch_panel_factor_nb<T, 4>(st, rpt, A, bstride, s, p0, nbw, tau, tmp)));
+    }
+    LR_TRY((launch_apply<T, true>(st, s.nb, A, bstride, A, bstride, s, p0, nbw, p0 + nbw, s.d, tmp)));
+  }
+  return hipSuccess;
+}
+
+// B[b] <- Q[b] B[b] with Q[b] from batched_qr (panels applied last to first).
+template <typename T>
+static hipError_t batched_apply_q(hipStream_t st, const T* V, int64_t vstride, T* B, int64_t bstride,
+                                  const QrShape& s, const T* tm) {
+  for (int p = s.npanels - 1; p >= 0; --p) {
+    const int p0 = p * s.nb;
+    const int nbw = (s.d - p0) < s.nb ? (s.d - p0) : s.nb;
+    LR_TRY((launch_apply<T, false>(st, s.nb, V, vstride, B, bstride, s, p0, nbw, 0, s.d,
+                                   tm + (int64_t)p * s.nb * s.nb)));
+  }
+  return hipSuccess;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct TsqrPlan {
+  int64_t n;
+  int d, leaf_rows, nleaf, m_last;
+  std::vector<int> count;  // R factors per level (level 0 = leaves)
+  std::vector<int> pairs;  // nodes per tree level
+  // offsets into the workspace
+  size_t off_work, off_tau, off_t;
+  std::vector<size_t> off_r, off_m, off_node, off_ntau, off_nt;
+  size_t total;
+};
+
+template <typename T>
+static TsqrPlan make_plan(int64_t n, int d, int leaf_rows) {
+  TsqrPlan p;
+  p.n = n;
+  p.d = d;
+  p.leaf_rows = leaf_rows;
+  p.nleaf = (int)((n + leaf_rows - 1) / leaf_rows);
+  p.m_last = (int)(n - (int64_t)(p.nleaf - 1) * leaf_rows);
+  QrShape ls = qr_shape<T>(leaf_rows, p.m_last, p.nleaf, d);
+  size_t off = 0;
+  p.off_work = off;
+  off = align256(off + (size_t)n * d * sizeof(T));
+  p.off_tau = off;
+  off = align256(off + (size_t)p.nleaf * d * sizeof(T));
+  p.off_t = off;
+  off = align256(off + (size_t)p.nleaf * ls.npanels * ls.nb * ls.nb * sizeof(T));
+  int c = p.nleaf;
+  p.count.push_back(c);
+  while (c > 1) {
+    p.pairs.push_back(c / 2);
+    c = (c + 1) / 2;
+    p.count.push_back(c);
+  }
+  const size_t dd = (size_t)d * d * sizeof(double);
+  for (size_t l = 0; l < p.count.size(); ++l) {
+    p.off_r.push_back(off);
+    off = align256(off + (size_t)p.count[l] * dd);
+    p.off_m.push_back(off);
+    off = align256(off + (size_t)p.count[l] * dd);
+  }
+  for (size_t l = 0; l < p.pairs.size(); ++l) {
+    QrShape ns = qr_shape<double>(2 * d, 2 * d, p.pairs[l], d);
+    p.off_node.push_back(off);
+    off = align256(off + (size_t)p.pairs[l] * 2 * dd);
+    p.off_ntau.push_back(off);
+    off = align256(off + (size_t)p.pairs[l] * d * sizeof(double));
+    p.off_nt.push_back(off);
+    off = align256(off + (size_t)p.pairs[l] * ns.npanels * ns.nb * ns.nb * sizeof(double));
+  }
+  p.total = off;
+  return p;
+}
+
+size_t tsqr_workspace(int64_t n, int d, int leaf_rows, bool f64) {
+  return f64 ? make_plan<double>(n, d, leaf_rows).total : make_plan<float>(n, d, leaf_rows).total;
+}
+
+template <typename T>
+static hipError_t launch_copy(hipStream_t st, const T* src, T* dst, int64_t count) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_kernel<T>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, src, dst, count);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t tsqr_run(hipStream_t st, int64_t n, int d, int leaf_rows, const T* Y, T* Q, double* R, void* ws) {
+  const TsqrPlan p = make_plan<T>(n, d, leaf_rows);
+  char* base = static_cast<char*>(ws);
+  T* work = reinterpret_cast<T*>(base + p.off_work);
+  T* tau = reinterpret_cast<T*>(base + p.off_tau);
+  T* tm = reinterpret_cast<T*>(base + p.off_t);
+  const QrShape ls = qr_shape<T>(leaf_rows, p.m_last, p.nleaf, d);
+  const int64_t lstride = (int64_t)leaf_rows * d;
+  const int64_t dd = (int64_t)d * d;
+  const unsigned ddblocks = (unsigned)((dd + 255) / 256);
+
+  // Eq. (1): leaf QRs on a working copy of Y.
+  LR_TRY(launch_copy<T>(st, Y, work, n * d));
+  LR_TRY(batched_qr<T>(st, work, lstride, ls, tau, tm));
+  double* r0 = reinterpret_cast<double*>(base + p.off_r[0]);
+  hipLaunchKernelGGL(extract_r_kernel<T>, dim3(ddblocks, p.nleaf), dim3(256), 0, st, work, lstride, d, d, r0,
+                     p.nleaf);
+  LR_TRY(hipGetLastError());
+
+  // Eq. (2)-(3): pairwise QR of stacked R factors, level by level.
+  const int levels = (int)p.pairs.size();
+  for (int l = 0; l < levels; ++l) {
+    const int np = p.pairs[l];
+    double* rin = reinterpret_cast<double*>(base + p.off_r[l]);
+    double* rout = reinterpret_cast<double*>(base + p.off_r[l + 1]);
+    double* node = reinterpret_cast<double*>(base + p.off_node[l]);
+    double* ntau = reinterpret_cast<double*>(base + p.off_ntau[l]);
+    double* nt = reinterpret_cast<double*>(base + p.off_nt[l]);
+    const QrShape ns = qr_shape<double>(2 * d, 2 * d, np, d);
+    LR_TRY(launch_copy<double>(st, rin, node, (int64_t)np * 2 * dd));  // pairs are adjacent in rin
+    LR_TRY(batched_qr<double>(st, node, 2 * dd, ns, ntau, nt));
+    hipLaunchKernelGGL(extract_r_kernel<double>, dim3(ddblocks, np), dim3(256), 0, st, node, 2 * dd, d, d, rout, np);
+    LR_TRY(hipGetLastError());
+    if (p.count[l] % 2 == 1)
+      LR_TRY(launch_copy<double>(st, rin + (int64_t)(p.count[l] - 1) * dd, rout + (int64_t)np * dd, dd));
+  }
+
+  // Root: R with diag >= 0, and the root block of Q's tree factor.
+  double* rroot = reinterpret_cast<double*>(base + p.off_r[levels]);
+  double* mroot = reinterpret_cast<double*>(base + p.off_m[levels]);
+  hipLaunchKernelGGL(finalize_r_kernel, dim3(ddblocks), dim3(256), 0, st, rroot, R, mroot, d);
+  LR_TRY(hipGetLastError());
+
+  // Eq. (4): push the d x d blocks down the tree.
+  for (int l = levels - 1; l >= 0; --l) {
+    const int np = p.pairs[l];
+    double* mup = reinterpret_cast<double*>(base + p.off_m[l + 1]);
+    double* mdn = reinterpret_cast<double*>(base + p.off_m[l]);
+    double* node = reinterpret_cast<double*>(base + p.off_node[l]);
+    double* nt = reinterpret_cast<double*>(base + p.off_nt[l]);
+    const QrShape ns = qr_shape<double>(2 * d, 2 * d, np, d);
+    // [M_up[k]; 0] into the pair slot (2k, 2k+1) of this level
+    const unsigned b2 = (unsigned)((2 * dd + 255) / 256);
+    hipLaunchKernelGGL(init_qblock_kernel<double>, dim3(b2, np), dim3(256), 0, st, mup, mdn, 2 * dd, 2 * d, 2 * d,
+                       np, d);
+    LR_TRY(hipGetLastError());
+    LR_TRY(batched_apply_q<double>(st, node, 2 * dd, mdn, 2 * dd, ns, nt));
+    if (p.count[l] % 2 == 1)
+      LR_TRY(launch_copy<double>(st, mup + (int64_t)np * dd, mdn + (int64_t)(p.count[l] - 1) * dd, dd));
+  }
+
+  // Leaves: Q rows = Q_leaf [M_leaf; 0].
+  double* m0 = reinterpret_cast<double*>(base + p.off_m[0]);
+  const unsigned lb = (unsigned)(((int64_t)leaf_rows * d + 255) / 256);
+  hipLaunchKernelGGL(init_qblock_kernel<T>, dim3(lb, p.nleaf), dim3(256), 0, st, m0, Q, lstride, leaf_rows,
+                     p.m_last, p.nleaf, d);
+  LR_TRY(hipGetLastError());
+  LR_TRY(batched_apply_q<T>(st, work, lstride, Q, lstride, ls, tm));
+  return hipSuccess;
+}
+
+template hipError_t tsqr_run<float>(hipStream_t, int64_t, int, int, const float*, float*, double*, void*);
+template hipError_t tsqr_run<double>(hipStream_t, int64_t, int, int, const double*, double*, double*, void*);
+
+}  // namespace lr
