@@ -186,7 +186,7 @@ lr_status woodbury_apply(hipStream_t st, int64_t n, int32_t d, int32_t m, int32_
 
 struct BackWs {
   size_t off_yp, off_sk, off_tn, off_e, off_a, off_h, off_p, off_aa, off_qx, off_qb, off_xy, off_by, off_xb, off_b,
-      off_z, off_w, off_scr, total;
+      off_z, off_w, off_phi, off_sinv, off_scr, total;
 };
 
 BackWs back_layout(int64_t n, int32_t D, int32_t d, int32_t m, int32_t prec) {
@@ -229,8 +229,12 @@ BackWs back_layout(int64_t n, int32_t D, int32_t d, int32_t m, int32_t prec) {
   off = al(off + (size_t)d * mm * 8);
   w.off_w = off;
   off = al(off + (size_t)d * mm * 8);
+  w.off_phi = off;
+  off = al(off + (size_t)d * d * 8);
+  w.off_sinv = off;
+  off = al(off + (size_t)d * d * 8);
   w.off_scr = off;
-  off = al(off + (size_t)4 * d * d * 8);
+  off = al(off + (size_t)3 * d * d * 8);
   w.total = off;
   return w;
 }
@@ -412,6 +416,16 @@ lr_status lr_backward(void* stream, int64_t n, int32_t D, const float* X, const 
   b.E = reinterpret_cast<double*>(base + w.off_e);
   b.scratch = reinterpret_cast<double*>(base + w.off_scr);
   b.dtheta = dtheta;
+  double* phi = reinterpret_cast<double*>(base + w.off_phi);
+  LR_HIP(launch_identity(st, phi, d));
+  LR_HIP(launch_solve_cols(st, 0, d, d, Flu, piv, nullptr, phi, d, nullptr));
+  b.Phi = phi;
+  if (mode == 0) {
+    double* sinv = reinterpret_cast<double*>(base + w.off_sinv);
+    LR_HIP(launch_identity(st, sinv, d));
+    LR_HIP(launch_solve_cols(st, 1, d, d, L, nullptr, nullptr, sinv, d, nullptr));
+    b.Sinv = sinv;
+  }
   LR_HIP(launch_gemm_tn(st, n, d, d, om, ypo, oscale, const_cast<double*>(b.E), tn, f64));
   if (mode == 0) {
     const TnOperand al_ = real_operand(U, 1, prec);

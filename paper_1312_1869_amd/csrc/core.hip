@@ -1,14 +1,15 @@
 // The d x d float64 core of the Woodbury-form approximation and of its adjoint.
 //
-// Forward (one 1024-thread workgroup; d <= 1024):
-//   LU with partial pivoting of F = Omega^T Q (LAPACK getrf convention: whole
-//   rows swapped, first index of the largest magnitude as pivot), C = F^{-1} R^T
-//   by forward/backward substitution (one thread per right-hand side),
-//   C <- (C + C^T)/2, S = C + (sigma2 - nu) I, Cholesky S = L L^T, and
-//   log|K~| = (n - d) log sigma2 + 2 sum log L_jj.
+// Forward (d <= 1024):
+//   LU with partial pivoting of F = Omega^T Q (one 1024-thread workgroup;
+//   LAPACK getrf convention: whole rows swapped, first index of the largest
+//   magnitude as pivot); C = F^{-1} R^T by forward/backward substitution, one
+//   wave per right-hand side; C <- (C + C^T)/2, S = C + (sigma2 - nu) I,
+//   Cholesky S = L L^T and log|K~| = (n - d) log sigma2 + 2 sum log L_jj (one
+//   workgroup).
 //   info = -k for a zero LU pivot at step k, k for the k-th non-positive
 //   Cholesky pivot (1-based), 0 on success.
-// The small solve W' = S^{-1} Z - Z / sigma2 runs one wave per column of Z.
+// The small solve W' = S^{-1} Z - Z / sigma2 uses the same column solver.
 // The backward kernel evaluates the d x d contractions of the hyperparameter
 // adjoint (formulas in lrinv.h / the oracle's grad module).
 #include "common.hpp"
@@ -106,31 +107,6 @@ __device__ int lu_inplace(double* A, int32_t* piv, int d, double* redv, int* red
   return 0;
 }
 
-// X (d x nrhs, row-major, column c handled by thread c) <- A^{-1} X with the
-// LU factors and pivots of lu_inplace.
-__device__ void lu_solve_cols(const double* LU, const int32_t* piv, int d, double* X, int nrhs, int ldx) {
-  for (int c = threadIdx.x; c < nrhs; c += kCoreThreads) {
-    for (int k = 0; k < d; ++k) {
-      const int p = piv[k];
-      if (p != k) {
-        const double x = X[(int64_t)k * ldx + c];
-        X[(int64_t)k * ldx + c] = X[(int64_t)p * ldx + c];
-        X[(int64_t)p * ldx + c] = x;
-      }
-    }
-    for (int i = 1; i < d; ++i) {
-      double s = X[(int64_t)i * ldx + c];
-      for (int k = 0; k < i; ++k) s -= LU[(int64_t)i * d + k] * X[(int64_t)k * ldx + c];
-      X[(int64_t)i * ldx + c] = s;
-    }
-    for (int i = d - 1; i >= 0; --i) {
-      double s = X[(int64_t)i * ldx + c];
-      for (int k = i + 1; k < d; ++k) s -= LU[(int64_t)i * d + k] * X[(int64_t)k * ldx + c];
-      X[(int64_t)i * ldx + c] = s / LU[(int64_t)i * d + i];
-    }
-  }
-}
-
 // Cholesky in place on the lower triangle of L (row-major). Returns 0 or k+1.
 __device__ int chol_inplace(double* L, int d) {
   const int t = threadIdx.x;
@@ -155,34 +131,127 @@ __device__ int chol_inplace(double* L, int d) {
   return 0;
 }
 
-__global__ __launch_bounds__(kCoreThreads) void core_kernel(int64_t n, int d, const double* __restrict__ F,
-                                                            const double* __restrict__ R, double sigma2, double nu,
-                                                            double* Flu, int32_t* piv, double* C, double* L,
-                                                            double* logdet, int32_t* info) {
+// ---- forward core, three launches: LU(F); C = F^{-1} R^T (one wave per
+// right-hand side); symmetrise + shift + Cholesky + log-determinant.
+
+__global__ __launch_bounds__(kCoreThreads) void lu_kernel(int d, const double* __restrict__ F, double* Flu,
+                                                          int32_t* piv, int32_t* info, double* logdet) {
   __shared__ double redv[kCoreWaves];
   __shared__ int redi[kCoreWaves];
-  __shared__ double red[kCoreWaves];
   const int t = threadIdx.x;
   const int64_t dd = (int64_t)d * d;
   for (int64_t e = t; e < dd; e += kCoreThreads) Flu[e] = F[e];
   __syncthreads();
   const int lu = lu_inplace(Flu, piv, d, redv, redi);
-  if (lu != 0) {
-    if (t == 0) {
-      *info = lu;
-      *logdet = __builtin_nan("");
+  if (t == 0) {
+    *info = lu;
+    if (lu != 0) *logdet = __builtin_nan("");
+  }
+}
+
+// Solve in place, for every column c of X (d x nrhs, leading dimension ldx):
+//   mode 0: X <- A^{-1} X with A = P L U from lu_inplace (pivots applied first);
+//   mode 1: X <- S^{-1} X with S = L L^T (lower Cholesky factor);
+//   mode 2: as 0, with the right-hand side read as B[c][i] = src[c * d + i]
+//           (i.e. the solve of A X = src^T), written to X.
+// One wave per column; the column lives in LDS; the next row of the factor is
+// prefetched into registers while the current row's dot product completes.
+// Skipped when *info != 0.
+constexpr int kSolveWaves = 4;
+constexpr int kSolvePer = 16;  // d / 64 rounded up, d <= 1024
+
+template <bool UNIT, bool LOWER, bool TRANSF>
+__device__ __forceinline__ void wave_trisolve(const double* __restrict__ Fm, int d, double* y, int lane) {
+  // LOWER: y_i = (y_i - sum_{k<i} F[i][k] y_k) / (UNIT ? 1 : F[i][i])
+  // !LOWER with TRANSF: y_i = (y_i - sum_{k>i} F[k][i] y_k) / F[i][i]   (F^T upper)
+  // !LOWER without TRANSF: y_i = (y_i - sum_{k>i} F[i][k] y_k) / F[i][i]
+  double nxt[kSolvePer];
+  auto load_row = [&](int i, double (&buf)[kSolvePer]) {
+#pragma unroll
+    for (int q = 0; q < kSolvePer; ++q) {
+      const int k = lane + 64 * q;
+      bool use;
+      if (LOWER) use = k < i;
+      else use = k > i && k < d;
+      buf[q] = use ? (TRANSF ? Fm[(int64_t)k * d + i] : Fm[(int64_t)i * d + k]) : 0.0;
     }
-    return;
+  };
+  const int first = LOWER ? 0 : d - 1;
+  const int step = LOWER ? 1 : -1;
+  load_row(first, nxt);
+  for (int it = 0; it < d; ++it) {
+    const int i = first + step * it;
+    double cur[kSolvePer];
+#pragma unroll
+    for (int q = 0; q < kSolvePer; ++q) cur[q] = nxt[q];
+    if (it + 1 < d) load_row(i + step, nxt);
+    double part = 0.0;
+#pragma unroll
+    for (int q = 0; q < kSolvePer; ++q) {
+      const int k = lane + 64 * q;
+      if (k < d) part += cur[q] * y[k];
+    }
+    part = wave_sum(part);
+    const double diag = UNIT ? 1.0 : Fm[(int64_t)i * d + i];
+    const double yi = (y[i] - part) / diag;
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) y[i] = yi;
+    __builtin_amdgcn_wave_barrier();
   }
-  // C = F^{-1} R^T
-  for (int64_t e = t; e < dd; e += kCoreThreads) {
-    const int i = (int)(e / d), j = (int)(e % d);
-    C[e] = R[(int64_t)j * d + i];
+}
+
+__global__ __launch_bounds__(64 * kSolveWaves) void solve_cols_kernel(int mode, int d, int nrhs, const double* Fm,
+                                                                      const int32_t* __restrict__ piv,
+                                                                      const double* __restrict__ src, double* X,
+                                                                      int ldx, const int32_t* __restrict__ info) {
+  extern __shared__ double ybuf[];
+  if (info != nullptr && *info != 0) return;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = blockIdx.x * kSolveWaves + w;
+  if (c >= nrhs) return;
+  double* y = ybuf + (int64_t)w * d;
+  for (int i = lane; i < d; i += 64) y[i] = (mode == 2) ? src[(int64_t)c * d + i] : X[(int64_t)i * ldx + c];
+  __builtin_amdgcn_wave_barrier();
+  if (mode != 1) {
+    if (lane == 0) {
+      for (int k = 0; k < d; ++k) {
+        const int p = piv[k];
+        if (p != k) {
+          const double tmp = y[k];
+          y[k] = y[p];
+          y[p] = tmp;
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    wave_trisolve<true, true, false>(Fm, d, y, lane);   // unit lower L
+    wave_trisolve<false, false, false>(Fm, d, y, lane); // upper U
+  } else {
+    wave_trisolve<false, true, false>(Fm, d, y, lane);  // L
+    wave_trisolve<false, false, true>(Fm, d, y, lane);  // L^T
   }
-  __syncthreads();
-  lu_solve_cols(Flu, piv, d, C, d, d);
-  __syncthreads();
-  // symmetrise; S = C + (sigma2 - nu) I into the lower triangle of L
+  __builtin_amdgcn_wave_barrier();
+  for (int i = lane; i < d; i += 64) X[(int64_t)i * ldx + c] = y[i];
+}
+
+hipError_t launch_solve_cols(hipStream_t st, int mode, int d, int nrhs, const double* Fm, const int32_t* piv,
+                             const double* src, double* X, int ldx, const int32_t* info) {
+  if (nrhs <= 0) return hipSuccess;
+  const size_t lds = (size_t)kSolveWaves * d * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)solve_cols_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(solve_cols_kernel, dim3((unsigned)((nrhs + kSolveWaves - 1) / kSolveWaves)),
+                     dim3(64 * kSolveWaves), lds, st, mode, d, nrhs, Fm, piv, src, X, ldx, info);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kCoreThreads) void chol_kernel(int64_t n, int d, double sigma2, double nu, double* C,
+                                                            double* L, double* logdet, int32_t* info) {
+  __shared__ double red[kCoreWaves];
+  if (*info != 0) return;
+  const int t = threadIdx.x;
+  const int64_t dd = (int64_t)d * d;
   const double shift = sigma2 - nu;
   for (int64_t e = t; e < dd; e += kCoreThreads) {
     const int i = (int)(e / d), j = (int)(e % d);
@@ -209,16 +278,18 @@ __global__ __launch_bounds__(kCoreThreads) void core_kernel(int64_t n, int d, co
   double part = 0.0;
   for (int k = t; k < d; k += kCoreThreads) part += log(L[(int64_t)k * d + k]);
   const double s = block_sum(part, red);
-  if (t == 0) {
-    *info = 0;
-    *logdet = (double)(n - d) * log(sigma2) + 2.0 * s;
-  }
+  if (t == 0) *logdet = (double)(n - d) * log(sigma2) + 2.0 * s;
 }
 
 hipError_t launch_core(hipStream_t st, int64_t n, int d, const double* F, const double* R, double sigma2, double nu,
                        double* Flu, int32_t* piv, double* C, double* L, double* logdet, int32_t* info) {
-  hipLaunchKernelGGL(core_kernel, dim3(1), dim3(kCoreThreads), 0, st, n, d, F, R, sigma2, nu, Flu, piv, C, L, logdet,
-                     info);
+  hipLaunchKernelGGL(lu_kernel, dim3(1), dim3(kCoreThreads), 0, st, d, F, Flu, piv, info, logdet);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // C = F^{-1} R^T: column c of R^T is row c of R
+  e = launch_solve_cols(st, 2, d, d, Flu, piv, R, C, d, info);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(kCoreThreads), 0, st, n, d, sigma2, nu, C, L, logdet, info);
   return hipGetLastError();
 }
 
@@ -252,46 +323,23 @@ hipError_t launch_loglik(hipStream_t st, int64_t n, bool f64, const void* y, con
 
 // ------------------------------------------------------------------ S^{-1} Z
 
-__global__ __launch_bounds__(256) void core_apply_kernel(int d, int m, const double* __restrict__ L,
-                                                         const double* __restrict__ Z, double sigma2,
-                                                         const int32_t* __restrict__ info, double* __restrict__ W) {
-  extern __shared__ double ybuf[];  // 4 waves x d
+__global__ void sub_scaled_kernel(int64_t count, const double* __restrict__ Z, double inv_sigma2,
+                                  const int32_t* __restrict__ info, double* __restrict__ W) {
   if (info != nullptr && *info != 0) return;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int c = blockIdx.x * 4 + w;
-  if (c >= m) return;
-  double* y = ybuf + (int64_t)w * d;
-  // forward: L y = z
-  for (int i = 0; i < d; ++i) {
-    double part = 0.0;
-    for (int k = lane; k < i; k += 64) part += L[(int64_t)i * d + k] * y[k];
-    part = wave_sum(part);
-    const double yi = (Z[(int64_t)i * m + c] - part) / L[(int64_t)i * d + i];
-    if (lane == 0) y[i] = yi;
-    __builtin_amdgcn_wave_barrier();
-  }
-  // backward: L^T x = y (x overwrites y from the end)
-  for (int i = d - 1; i >= 0; --i) {
-    double part = 0.0;
-    for (int k = i + 1 + lane; k < d; k += 64) part += L[(int64_t)k * d + i] * y[k];
-    part = wave_sum(part);
-    const double xi = (y[i] - part) / L[(int64_t)i * d + i];
-    __builtin_amdgcn_wave_barrier();
-    if (lane == 0) y[i] = xi;
-    __builtin_amdgcn_wave_barrier();
-  }
-  for (int i = lane; i < d; i += 64) W[(int64_t)i * m + c] = y[i] - Z[(int64_t)i * m + c] / sigma2;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx < count) W[idx] -= Z[idx] * inv_sigma2;
 }
 
 hipError_t launch_core_apply(hipStream_t st, int d, int m, const double* L, const double* Z, double sigma2,
                              const int32_t* info, double* Wout) {
   if (m <= 0) return hipSuccess;
-  const size_t lds = (size_t)4 * d * sizeof(double);
-  hipError_t e = hipFuncSetAttribute((const void*)core_apply_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
+  const int64_t count = (int64_t)d * m;
+  hipError_t e = hipMemcpyAsync(Wout, Z, (size_t)count * sizeof(double), hipMemcpyDeviceToDevice, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(core_apply_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), lds, st, d, m, L, Z, sigma2, info,
-                     Wout);
+  e = launch_solve_cols(st, 1, d, m, L, nullptr, nullptr, Wout, m, info);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sub_scaled_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count, Z,
+                     1.0 / sigma2, info, Wout);
   return hipGetLastError();
 }
 
@@ -313,41 +361,20 @@ __global__ __launch_bounds__(kCoreThreads) void backward_small_kernel(BackwardSm
   const int t = threadIdx.x;
   const int d = b.d;
   const int64_t dd = (int64_t)d * d;
-  double* Phi = b.scratch;            // F^{-1}
-  double* Mq = b.scratch + dd;        // Q^T G Q
-  double* T1 = b.scratch + 2 * dd;    // work
-  double* T2 = b.scratch + 3 * dd;    // work
-
-  // Phi = F^{-1}
-  for (int64_t e = t; e < dd; e += kCoreThreads) Phi[e] = ((e / d) == (e % d)) ? 1.0 : 0.0;
-  __syncthreads();
-  lu_solve_cols(b.Flu, b.piv, d, Phi, d, d);
-  __syncthreads();
+  const double* Phi = b.Phi;          // F^{-1} (precomputed)
+  double* Mq = b.scratch;             // Q^T G Q
+  double* T1 = b.scratch + dd;        // work
+  double* T2 = b.scratch + 2 * dd;    // work
 
   double dlogell_t1 = 0.0, trace_g = 0.0;
   if (b.mode == 0) {
-    // S^{-1} into T1 (columns by forward/backward substitution with L)
-    for (int64_t e = t; e < dd; e += kCoreThreads) T1[e] = ((e / d) == (e % d)) ? 1.0 : 0.0;
-    __syncthreads();
-    for (int c = t; c < d; c += kCoreThreads) {
-      for (int i = 0; i < d; ++i) {
-        double s = T1[(int64_t)i * d + c];
-        for (int k = 0; k < i; ++k) s -= b.L[(int64_t)i * d + k] * T1[(int64_t)k * d + c];
-        T1[(int64_t)i * d + c] = s / b.L[(int64_t)i * d + i];
-      }
-      for (int i = d - 1; i >= 0; --i) {
-        double s = T1[(int64_t)i * d + c];
-        for (int k = i + 1; k < d; ++k) s -= b.L[(int64_t)k * d + i] * T1[(int64_t)k * d + c];
-        T1[(int64_t)i * d + c] = s / b.L[(int64_t)i * d + i];
-      }
-    }
-    __syncthreads();
+    const double* Sinv = b.Sinv;      // S^{-1} (precomputed)
     // Mq = (a a^T - S^{-1}) / 2 ; tr S^{-1}
     double tr = 0.0;
     for (int64_t e = t; e < dd; e += kCoreThreads) {
       const int i = (int)(e / d), j = (int)(e % d);
-      Mq[e] = 0.5 * (b.a[i] * b.a[j] - T1[e]);
-      if (i == j) tr += T1[e];
+      Mq[e] = 0.5 * (b.a[i] * b.a[j] - Sinv[e]);
+      if (i == j) tr += Sinv[e];
     }
     const double tr_sinv = block_sum(tr, red);
     // (Phi^T a) . h
@@ -360,7 +387,7 @@ __global__ __launch_bounds__(kCoreThreads) void backward_small_kernel(BackwardSm
     const double t1a = block_sum(p1, red);
     __syncthreads();
     // <S^{-1} Phi, P>
-    matmul_dd(T1, Phi, T2, d);
+    matmul_dd(Sinv, Phi, T2, d);
     __syncthreads();
     double p2 = 0.0;
     for (int64_t e = t; e < dd; e += kCoreThreads) p2 += T2[e] * b.P[e];

@@ -71,9 +71,16 @@ struct BackwardSmall {
   const double* XY;     // mode 1: X^T Y' (m x d)
   const double* BY;     // mode 1: B^T Y' (m x d)
   const double* XB;     // mode 1: X^T B (m x m)
-  double* scratch;      // 4 d*d doubles
+  const double* Phi;    // F^{-1} (d x d)
+  const double* Sinv;   // mode 0: S^{-1} (d x d)
+  double* scratch;      // 3 d*d doubles
   double* dtheta;
 };
 hipError_t launch_backward_small(hipStream_t st, const BackwardSmall& b);
+// Column-wise dense solves (see core.hip): mode 0 LU (P L U), 1 Cholesky (L L^T),
+// 2 LU with the right-hand side read transposed from src. Skipped when *info != 0.
+hipError_t launch_solve_cols(hipStream_t st, int mode, int d, int nrhs, const double* Fm, const int32_t* piv,
+                             const double* src, double* X, int ldx, const int32_t* info);
+hipError_t launch_identity(hipStream_t st, double* X, int d);
 
 }  // namespace lr

@@ -166,6 +166,17 @@ hipError_t launch_fill(hipStream_t st, double* out, int64_t count, double v) {
   return hipGetLastError();
 }
 
+__global__ void identity_kernel(double* __restrict__ X, int d) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx < (int64_t)d * d) X[idx] = (idx / d == idx % d) ? 1.0 : 0.0;
+}
+
+hipError_t launch_identity(hipStream_t st, double* X, int d) {
+  const int64_t count = (int64_t)d * d;
+  hipLaunchKernelGGL(identity_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, X, d);
+  return hipGetLastError();
+}
+
 __global__ void reduce_partials_kernel(const double* __restrict__ partial, int64_t nchunk, int64_t count,
                                        double scale, double* __restrict__ out) {
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;

@@ -49,35 +49,64 @@ __device__ __forceinline__ void block_sum_vec(T (&v)[NV], int nvalid, T* red, T*
     if (i < nvalid) v[i] = res[i];
 }
 
-// Factor columns [p0, p0 + nbw) of every matrix in the batch (rows p0 .. m-1).
+// Rows a panel touches. Plain mode: rows p0 .. m-1. Tree mode (tree_d = d > 0,
+// the matrix is a stacked pair [R_a; R_b] of upper triangles): reflectors of
+// columns < p0 + NB can only be nonzero in the top rows p0 .. p0+NB-1 and the
+// bottom rows d .. d+p0+NB-1 (R_a's lower rows and R_b's rows below the panel
+// are still exact zeros there), so only those rows are visited.
+struct RowMap {
+  int p0, ntop, nact, d;
+  __device__ __forceinline__ int row(int ci) const { return ci < ntop ? p0 + ci : d + (ci - ntop); }
+};
+
+template <int NB>
+__device__ __forceinline__ RowMap make_rowmap(int m, int p0, int tree_d) {
+  RowMap rm;
+  rm.p0 = p0;
+  rm.d = tree_d;
+  if (tree_d > 0) {
+    rm.ntop = min(NB, tree_d - p0);
+    const int nbot = min(p0 + NB, tree_d);
+    rm.nact = rm.ntop + nbot;
+  } else {
+    rm.ntop = m - p0;
+    rm.nact = m - p0;
+  }
+  return rm;
+}
+
+// Factor columns [p0, p0 + nbw) of every matrix in the batch.
 template <typename T, int RPT, int NB>
 __global__ __launch_bounds__(kPanelThreads) void panel_factor_kernel(T* __restrict__ A, int64_t bstride, int m_full,
                                                                      int m_last, int nbatch, int ld, int p0, int nbw,
-                                                                     T* __restrict__ tau_all, int64_t tau_bstride,
-                                                                     T* __restrict__ tmat, int64_t t_bstride) {
+                                                                     int tree_d, T* __restrict__ tau_all,
+                                                                     int64_t tau_bstride, T* __restrict__ tmat,
+                                                                     int64_t t_bstride) {
   __shared__ T red[kPanelWaves * NB];
   __shared__ T res[NB];
   __shared__ T s_alpha;
   __shared__ T s_tau[NB];
   __shared__ T s_y[NB * NB];  // s_y[c * NB + c1] = (V^T v_c)[c1], c1 < c
+  __shared__ T s_t[NB * NB];
 
   const int b = blockIdx.x;
   const int m = (b == nbatch - 1) ? m_last : m_full;
   T* M = A + (int64_t)b * bstride;
-  const int rows = m - p0;
+  const RowMap rm = make_rowmap<NB>(m, p0, tree_d);
+  const int rows = rm.nact;
   const int t = threadIdx.x;
 
   T a[RPT][NB];
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     const int lr = t + k * kPanelThreads;
+    const int64_t roff = (lr < rows) ? (int64_t)rm.row(lr) * ld + p0 : 0;
 #pragma unroll
-    for (int c = 0; c < NB; ++c)
-      a[k][c] = (lr < rows && c < nbw) ? M[(int64_t)(p0 + lr) * ld + p0 + c] : (T)0;
+    for (int c = 0; c < NB; ++c) a[k][c] = (lr < rows && c < nbw) ? M[roff + c] : (T)0;
   }
 
   for (int c = 0; c < nbw; ++c) {
-    // sigma = |x below the diagonal|^2 ; alpha = diagonal entry
+    // sigma = |x below the diagonal|^2 ; alpha = diagonal entry (compact row c)
     T part[1] = {0};
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
@@ -99,7 +128,6 @@ __global__ __launch_bounds__(kPanelThreads) void panel_factor_kernel(T* __restri
       tau = (beta - alpha) / beta;
       scal = (T)1 / (alpha - beta);
     }
-    // reflector v (unit at the diagonal), R diagonal entry
     T vk[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
@@ -134,7 +162,6 @@ __global__ __launch_bounds__(kPanelThreads) void panel_factor_kernel(T* __restri
       for (int i = 0; i < NB; ++i)
         if (i < c) s_y[c * NB + i] = wv[i];
     }
-    // apply H = I - tau v v^T to the remaining panel columns
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
 #pragma unroll
@@ -149,37 +176,42 @@ __global__ __launch_bounds__(kPanelThreads) void panel_factor_kernel(T* __restri
   for (int k = 0; k < RPT; ++k) {
     const int lr = t + k * kPanelThreads;
     if (lr < rows) {
+      const int64_t roff = (int64_t)rm.row(lr) * ld + p0;
 #pragma unroll
       for (int c = 0; c < NB; ++c)
-        if (c < nbw) M[(int64_t)(p0 + lr) * ld + p0 + c] = a[k][c];
+        if (c < nbw) M[roff + c] = a[k][c];
     }
   }
+  // T (upper triangular, LDS): T[c][c] = tau_c, T[0:c, c] = -tau_c T[0:c, 0:c] y_c
   if (t == 0) {
-    T* tau_b = tau_all + (int64_t)b * tau_bstride;
-    for (int c = 0; c < nbw; ++c) tau_b[p0 + c] = s_tau[c];
-    // T: upper triangular, T[c][c] = tau_c, T[0:c, c] = -tau_c T[0:c, 0:c] y_c
-    T* Tm = tmat + (int64_t)b * t_bstride;
-    for (int i = 0; i < NB * NB; ++i) Tm[i] = 0;
+    for (int i = 0; i < NB * NB; ++i) s_t[i] = 0;
     for (int c = 0; c < nbw; ++c) {
       const T tc = s_tau[c];
       for (int r = 0; r < c; ++r) {
         T s = 0;
-        for (int q = r; q < c; ++q) s += Tm[r * NB + q] * s_y[c * NB + q];
-        Tm[r * NB + c] = -tc * s;
+        for (int q = r; q < c; ++q) s += s_t[r * NB + q] * s_y[c * NB + q];
+        s_t[r * NB + c] = -tc * s;
       }
-      Tm[c * NB + c] = tc;
+      s_t[c * NB + c] = tc;
     }
   }
+  __syncthreads();
+  if (t < NB * NB) tmat[(int64_t)b * t_bstride + t] = s_t[t];
+  if (t < nbw) tau_all[(int64_t)b * tau_bstride + p0 + t] = s_tau[t];
 }
 
-// B[p0:, cols] <- (I - V T' V^T) B[p0:, cols], T' = T^T (TRANS) or T.
-// V occupies columns [p0, p0 + NB) of Vmat (unit diagonal, zeros above).
+// B[rows, cols] <- (I - V T' V^T) B[rows, cols], T' = T^T (TRANS) or T, over the
+// rows of the panel's row map. V occupies columns [p0, p0 + NB) of Vmat (unit
+// diagonal, zeros above). V is staged through LDS in chunks of kApplyChunk rows.
+constexpr int kApplyChunk = 64;
+
 template <typename T, int NB, bool TRANS>
 __global__ __launch_bounds__(kUpdThreads) void panel_apply_kernel(const T* Vmat, int64_t vstride, T* Bmat,
                                                                   int64_t bstride, int m_full, int m_last,
-                                                                  int nbatch, int ld, int p0, int nbw,
+                                                                  int nbatch, int ld, int p0, int nbw, int tree_d,
                                                                   int col_begin, int col_end,
                                                                   const T* __restrict__ tmat, int64_t t_bstride) {
+  __shared__ T vch[kApplyChunk][NB];
   __shared__ T red[4][NB][kUpdCols];
   __shared__ T wsh[NB][kUpdCols];
   __shared__ T Ts[NB * NB];
@@ -188,39 +220,46 @@ __global__ __launch_bounds__(kUpdThreads) void panel_apply_kernel(const T* Vmat,
   const int m = (b == nbatch - 1) ? m_last : m_full;
   const T* V = Vmat + (int64_t)b * vstride;
   T* B = Bmat + (int64_t)b * bstride;
-  const int rows = m - p0;
+  const RowMap rm = make_rowmap<NB>(m, p0, tree_d);
+  const int nact = rm.nact;
   const int t = threadIdx.x;
   const int cl = t & (kUpdCols - 1);
   const int rg = wave_uniform(t >> 6);
   const int col = col_begin + blockIdx.x * kUpdCols + cl;
   const bool col_ok = col < col_end;
+  const int colc = col_ok ? col : col_begin;  // in-bounds column for loads
 
   if (t < NB * NB) Ts[t] = tmat[(int64_t)b * t_bstride + t];
+
+  auto stage = [&](int c0) {
+    for (int e = t; e < kApplyChunk * NB; e += kUpdThreads) {
+      const int r = e / NB, i = e % NB;
+      const int ci = c0 + r;
+      T val = 0;
+      if (ci < nact && i < nbw) {
+        if (ci > i)
+          val = V[(int64_t)rm.row(ci) * ld + p0 + i];
+        else if (ci == i)
+          val = (T)1;
+      }
+      vch[r][i] = val;
+    }
+  };
 
   T acc[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) acc[i] = 0;
-  // rows inside the triangular top of V
-  for (int lr = rg; lr < NB && lr < rows; lr += 4) {
-    const T x = col_ok ? B[(int64_t)(p0 + lr) * ld + col] : (T)0;
-    const T* vr = V + (int64_t)(p0 + lr) * ld + p0;
+  for (int c0 = 0; c0 < nact; c0 += kApplyChunk) {
+    stage(c0);
+    __syncthreads();
+#pragma unroll 4
+    for (int r = rg; r < kApplyChunk; r += 4) {
+      const int ci = c0 + r;
+      const T x = (ci < nact) ? B[(int64_t)rm.row(ci < nact ? ci : 0) * ld + colc] : (T)0;
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const T vl = vr[i < nbw ? i : 0];  // index kept inside the panel
-      const T vi = (i < lr && i < nbw) ? vl : (i == lr && i < nbw ? (T)1 : (T)0);
-      acc[i] += vi * x;
+      for (int i = 0; i < NB; ++i) acc[i] += vch[r][i] * x;
     }
-  }
-  const int lr0 = NB + ((rg - NB % 4 + 4) % 4);
-  for (int lr = lr0; lr < rows; lr += 4) {
-    const T x = col_ok ? B[(int64_t)(p0 + lr) * ld + col] : (T)0;
-    const T* vr = V + (int64_t)(p0 + lr) * ld + p0;
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const T vl = vr[i < nbw ? i : 0];
-      const T vi = (i < nbw) ? vl : (T)0;
-      acc[i] += vi * x;
-    }
+    __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < NB; ++i) red[rg][i][cl] = acc[i];
@@ -250,28 +289,20 @@ __global__ __launch_bounds__(kUpdThreads) void panel_apply_kernel(const T* Vmat,
   T wl[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) wl[i] = wsh[i][cl];
-  if (!col_ok) return;
-  for (int lr = rg; lr < NB && lr < rows; lr += 4) {
-    const T* vr = V + (int64_t)(p0 + lr) * ld + p0;
-    T s = 0;
+  for (int c0 = 0; c0 < nact; c0 += kApplyChunk) {
+    stage(c0);
+    __syncthreads();
+#pragma unroll 4
+    for (int r = rg; r < kApplyChunk; r += 4) {
+      const int ci = c0 + r;
+      if (ci < nact && col_ok) {
+        T s = 0;
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const T vl = vr[i < nbw ? i : 0];
-      const T vi = (i < lr && i < nbw) ? vl : (i == lr && i < nbw ? (T)1 : (T)0);
-      s += vi * wl[i];
+        for (int i = 0; i < NB; ++i) s += vch[r][i] * wl[i];
+        B[(int64_t)rm.row(ci) * ld + col] -= s;
+      }
     }
-    B[(int64_t)(p0 + lr) * ld + col] -= s;
-  }
-  for (int lr = lr0; lr < rows; lr += 4) {
-    const T* vr = V + (int64_t)(p0 + lr) * ld + p0;
-    T s = 0;
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const T vl = vr[i < nbw ? i : 0];
-      const T vi = (i < nbw) ? vl : (T)0;
-      s += vi * wl[i];
-    }
-    B[(int64_t)(p0 + lr) * ld + col] -= s;
+    __syncthreads();
   }
 }
 
@@ -335,16 +366,18 @@ static int pick_nb(int rpt) {
 }
 
 struct QrShape {
-  int m_full, m_last, nbatch, d, nb, npanels;
+  int m_full, m_last, nbatch, d, nb, npanels, tree_d;
 };
 
+// tree = true: every matrix is a stacked pair of d x d upper triangles.
 template <typename T>
-static QrShape qr_shape(int m_full, int m_last, int nbatch, int d) {
+static QrShape qr_shape(int m_full, int m_last, int nbatch, int d, bool tree = false) {
   QrShape s;
   s.m_full = m_full;
   s.m_last = m_last;
   s.nbatch = nbatch;
   s.d = d;
+  s.tree_d = tree ? d : 0;
   s.nb = pick_nb<T>(pick_rpt(m_full > m_last ? m_full : m_last));
   s.npanels = (d + s.nb - 1) / s.nb;
   return s;
@@ -354,7 +387,7 @@ template <typename T, int RPT, int NB>
 static hipError_t launch_panel_factor_rn(hipStream_t st, T* A, int64_t bstride, const QrShape& s, int p0, int nbw,
                                          T* tau, T* tm) {
   hipLaunchKernelGGL((panel_factor_kernel<T, RPT, NB>), dim3(s.nbatch), dim3(kPanelThreads), 0, st, A, bstride,
-                     s.m_full, s.m_last, s.nbatch, s.d, p0, nbw, tau, (int64_t)s.d, tm,
+                     s.m_full, s.m_last, s.nbatch, s.d, p0, nbw, s.tree_d, tau, (int64_t)s.d, tm,
                      (int64_t)s.npanels * NB * NB);
   return hipGetLastError();
 }
@@ -376,7 +409,7 @@ static hipError_t launch_apply_nb(hipStream_t st, const T* V, int64_t vstride, T
   if (c1 <= c0) return hipSuccess;
   const int ncb = (c1 - c0 + kUpdCols - 1) / kUpdCols;
   hipLaunchKernelGGL((panel_apply_kernel<T, NB, TRANS>), dim3(ncb, s.nbatch), dim3(kUpdThreads), 0, st, V, vstride,
-                     B, bstride, s.m_full, s.m_last, s.nbatch, s.d, p0, nbw, c0, c1, tm,
+                     B, bstride, s.m_full, s.m_last, s.nbatch, s.d, p0, nbw, s.tree_d, c0, c1, tm,
                      (int64_t)s.npanels * NB * NB);
   return hipGetLastError();
 }
@@ -472,7 +505,7 @@ static TsqrPlan make_plan(int64_t n, int d, int leaf_rows) {
     off = align256(off + (size_t)p.count[l] * dd);
   }
   for (size_t l = 0; l < p.pairs.size(); ++l) {
-    QrShape ns = qr_shape<double>(2 * d, 2 * d, p.pairs[l], d);
+    QrShape ns = qr_shape<double>(2 * d, 2 * d, p.pairs[l], d, true);
     p.off_node.push_back(off);
     off = align256(off + (size_t)p.pairs[l] * 2 * dd);
     p.off_ntau.push_back(off);
@@ -524,7 +557,7 @@ hipError_t tsqr_run(hipStream_t st, int64_t n, int d, int leaf_rows, const T* Y,
     double* node = reinterpret_cast<double*>(base + p.off_node[l]);
     double* ntau = reinterpret_cast<double*>(base + p.off_ntau[l]);
     double* nt = reinterpret_cast<double*>(base + p.off_nt[l]);
-    const QrShape ns = qr_shape<double>(2 * d, 2 * d, np, d);
+    const QrShape ns = qr_shape<double>(2 * d, 2 * d, np, d, true);
     LR_TRY(launch_copy<double>(st, rin, node, (int64_t)np * 2 * dd));  // pairs are adjacent in rin
     LR_TRY(batched_qr<double>(st, node, 2 * dd, ns, ntau, nt));
     hipLaunchKernelGGL(extract_r_kernel<double>, dim3(ddblocks, np), dim3(256), 0, st, node, 2 * dd, d, d, rout, np);
@@ -546,7 +579,7 @@ hipError_t tsqr_run(hipStream_t st, int64_t n, int d, int leaf_rows, const T* Y,
     double* mdn = reinterpret_cast<double*>(base + p.off_m[l]);
     double* node = reinterpret_cast<double*>(base + p.off_node[l]);
     double* nt = reinterpret_cast<double*>(base + p.off_nt[l]);
-    const QrShape ns = qr_shape<double>(2 * d, 2 * d, np, d);
+    const QrShape ns = qr_shape<double>(2 * d, 2 * d, np, d, true);
     // [M_up[k]; 0] into the pair slot (2k, 2k+1) of this level
     const unsigned b2 = (unsigned)((2 * dd + 255) / 256);
     hipLaunchKernelGGL(init_qblock_kernel<double>, dim3(b2, np), dim3(256), 0, st, mup, mdn, 2 * dd, 2 * d, 2 * d,
