@@ -122,12 +122,12 @@ lr_status sketch_impl(hipStream_t st, int64_t n, int32_t D, const float* X, cons
     if (prec == LR_PREC_F64) {
       double* pts = static_cast<double*>(ws);
       LR_HIP(launch_prep_points<double>(st, X, n, D, PD, scale, omega->signs, pts));
-      LR_HIP(launch_sketch_srht<double>(st, hyp->kernel, PD, pts, omega->cols, n, d, c * s2, nu * c,
+      LR_HIP(launch_sketch_srht<double>(st, hyp->kernel, D, pts, omega->cols, n, d, c * s2, nu * c,
                                         static_cast<double*>(Y), static_cast<double*>(Yp), ncu));
     } else {
       float* pts = static_cast<float*>(ws);
       LR_HIP(launch_prep_points<float>(st, X, n, D, PD, scale, omega->signs, pts));
-      LR_HIP(launch_sketch_srht<float>(st, hyp->kernel, PD, pts, omega->cols, n, d, c * s2, nu * c,
+      LR_HIP(launch_sketch_srht<float>(st, hyp->kernel, D, pts, omega->cols, n, d, c * s2, nu * c,
                                        static_cast<float*>(Y), static_cast<float*>(Yp), ncu));
     }
     return LR_OK;
@@ -138,9 +138,9 @@ lr_status sketch_impl(hipStream_t st, int64_t n, int32_t D, const float* X, cons
     LR_HIP(launch_prep_points<float>(st, X, n, D, PD, scale, nullptr, static_cast<float*>(ws)));
   }
   if (Y != nullptr)
-    LR_HIP(launch_sketch_dense(st, prec, hyp->kernel, PD, ws, omega->dense_t, omega->ld, n, d, s2, nu, Y, false, ncu));
+    LR_HIP(launch_sketch_dense(st, prec, hyp->kernel, D, ws, omega->dense_t, omega->ld, n, d, s2, nu, Y, false, ncu));
   if (Yp != nullptr)
-    LR_HIP(launch_sketch_dense(st, prec, hyp->kernel, PD, ws, omega->dense_t, omega->ld, n, d, s2, 0.0, Yp, true, ncu));
+    LR_HIP(launch_sketch_dense(st, prec, hyp->kernel, D, ws, omega->dense_t, omega->ld, n, d, s2, 0.0, Yp, true, ncu));
   return LR_OK;
 }
 

@@ -110,11 +110,31 @@ struct KernelT<float, KERNEL> : KernelF32<KERNEL> {};
 template <int KERNEL>
 struct KernelT<double, KERNEL> : KernelF64<KERNEL> {};
 
-// Wave-wide sum (64 lanes) with xor shuffles; every lane gets the total.
+// DPP lane moves (GFX9 encodings): quad_perm [1,0,3,2] and [2,3,0,1] swap
+// lanes xor 1 and xor 2; row_ror:4 and row_ror:8 rotate within 16-lane rows.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Wave-wide sum (64 lanes), every lane gets the total: four DPP steps give each
+// 16-lane row its sum, two xor shuffles combine the rows. Fixed order, so the
+// result is the same on every call.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  v += dpp_move<0xB1>(v);
+  v += dpp_move<0x4E>(v);
+  v += dpp_move<0x124>(v);
+  v += dpp_move<0x128>(v);
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
   return v;
 }
 

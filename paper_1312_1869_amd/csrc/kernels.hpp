@@ -12,9 +12,9 @@ template <typename T>
 hipError_t launch_prep_points(hipStream_t st, const float* X, int64_t n, int D, int PD, double scale,
                               const int8_t* signs, T* out);
 template <typename T>
-hipError_t launch_sketch_srht(hipStream_t st, int kernel, int PD, const T* pts, const int32_t* cols, int64_t n,
+hipError_t launch_sketch_srht(hipStream_t st, int kernel, int D, const T* pts, const int32_t* cols, int64_t n,
                               int d, double scale_out, double nu_c, T* Y, T* Yp, int num_cu);
-hipError_t launch_sketch_dense(hipStream_t st, int prec, int kernel, int PD, const void* pts, const void* omt,
+hipError_t launch_sketch_dense(hipStream_t st, int prec, int kernel, int D, const void* pts, const void* omt,
                                int64_t ld, int64_t n, int d, double scale_out, double nu, void* Y, bool deriv,
                                int num_cu);
 
