@@ -1,12 +1,11 @@
 // The d x d float64 core of the Woodbury-form approximation and of its adjoint.
 //
 // Forward (d <= 1024):
-//   LU with partial pivoting of F = Omega^T Q (one 1024-thread workgroup;
-//   LAPACK getrf convention: whole rows swapped, first index of the largest
-//   magnitude as pivot); C = F^{-1} R^T by forward/backward substitution, one
-//   wave per right-hand side; C <- (C + C^T)/2, S = C + (sigma2 - nu) I,
-//   Cholesky S = L L^T and log|K~| = (n - d) log sigma2 + 2 sum log L_jj (one
-//   workgroup).
+//   blocked LU with partial pivoting of F = Omega^T Q (LAPACK getrf
+//   convention: whole rows swapped, first index of the largest magnitude as
+//   pivot); C = F^{-1} R^T by forward/backward substitution, one wave per
+//   right-hand side; C <- (C + C^T)/2, S = C + (sigma2 - nu) I, blocked
+//   Cholesky S = L L^T and log|K~| = (n - d) log sigma2 + 2 sum log L_jj.
 //   info = -k for a zero LU pivot at step k, k for the k-th non-positive
 //   Cholesky pivot (1-based), 0 on success.
 // The small solve W' = S^{-1} Z - Z / sigma2 uses the same column solver.
@@ -31,9 +30,18 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
-// arg max |v| over the block; ties -> smallest index.
-__device__ __forceinline__ int block_argmax(double v, int idx, double* redv, int* redi) {
-  double a = fabs(v);
+// ---- blocked LU with partial pivoting (panels of kPanel columns).
+// Panel kernel: one workgroup, row k0 + t of the panel in thread t's
+// registers; per column a block arg-max (first index among equal magnitudes),
+// an exchange of the pivot row through LDS, scaling and a rank-1 update of
+// the remaining panel columns. Update kernel: one workgroup per 64 columns
+// outside the panel applies the panel's row exchanges to its columns and, to
+// the right of the panel, solves U12 = L11^{-1} A12 and updates
+// A22 -= L21 U12 (L21 staged through LDS).
+constexpr int kPanel = 32;
+
+__device__ __forceinline__ int block_argmax_db(double v, int idx, double* redv, int* redi, int& parity) {
+  double a = v;
   int i = idx;
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
@@ -45,112 +53,314 @@ __device__ __forceinline__ int block_argmax(double v, int idx, double* redv, int
     }
   }
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  __syncthreads();
+  double* bv = redv + parity * kCoreWaves;
+  int* bi = redi + parity * kCoreWaves;
+  parity ^= 1;
   if (lane == 0) {
-    redv[w] = a;
-    redi[w] = i;
+    bv[w] = a;
+    bi[w] = i;
   }
   __syncthreads();
   double ba = -1.0;
-  int bi = 0x7fffffff;
+  int best = 0x7fffffff;
   for (int k = 0; k < kCoreWaves; ++k) {
-    if (redv[k] > ba || (redv[k] == ba && redi[k] < bi)) {
-      ba = redv[k];
-      bi = redi[k];
+    if (bv[k] > ba || (bv[k] == ba && bi[k] < best)) {
+      ba = bv[k];
+      best = bi[k];
     }
   }
-  return bi;
+  return best;
 }
 
-// LU with partial pivoting in place (row-major d x d). Returns 0 or -(k+1).
-__device__ int lu_inplace(double* A, int32_t* piv, int d, double* redv, int* redi) {
+__global__ __launch_bounds__(kCoreThreads) void lu_panel_kernel(int d, double* A, int k0, int32_t* piv,
+                                                                int32_t* info, double* logdet) {
+  __shared__ double redv[2 * kCoreWaves];
+  __shared__ int redi[2 * kCoreWaves];
+  __shared__ double prow[2][kPanel];
+  __shared__ double krow[2][kPanel];
+  if (*info != 0) return;
   const int t = threadIdx.x;
-  for (int k = 0; k < d; ++k) {
-    double v = -1.0;
-    int vi = 0x7fffffff;
-    double best = -1.0;
-    for (int i = k + t; i < d; i += kCoreThreads) {
-      const double a = fabs(A[(int64_t)i * d + k]);
-      if (a > best) {
-        best = a;
-        vi = i;
-        v = a;
-      }
+  const int r = k0 + t;
+  const int nb = min(kPanel, d - k0);
+  const bool have = r < d;
+  double a[kPanel];
+#pragma unroll
+  for (int c = 0; c < kPanel; ++c) a[c] = (have && c < nb) ? A[(int64_t)r * d + k0 + c] : 0.0;
+  int par = 0;
+  for (int c = 0; c < nb; ++c) {
+    const int k = k0 + c;
+    // candidate magnitude on rows >= k (NaN never wins)
+    const double mag = (have && r >= k) ? fabs(a[c]) : -1.0;
+    int p = block_argmax_db(mag == mag ? mag : -1.0, have && r >= k ? r : 0x7fffffff, redv, redi, par);
+    if (p < k || p >= d) p = k;
+    const int buf = c & 1;
+    if (r == p) {
+#pragma unroll
+      for (int q = 0; q < kPanel; ++q) prow[buf][q] = a[q];
     }
-    if (vi == 0x7fffffff) v = -1.0;
-    int p = block_argmax(v, vi, redv, redi);
-    if (p < k || p >= d) p = k;  // column entirely NaN
+    if (r == k) {
+#pragma unroll
+      for (int q = 0; q < kPanel; ++q) krow[buf][q] = a[q];
+    }
+    __syncthreads();
+    const double pv = prow[buf][c];
+    if (!(fabs(pv) > 0.0)) {
+      if (t == 0) {
+        *info = -(k + 1);
+        *logdet = __builtin_nan("");
+      }
+      return;
+    }
     if (t == 0) piv[k] = p;
-    const double pv = A[(int64_t)p * d + k];
-    __syncthreads();  // every thread has read the pivot before rows move
-    if (!(fabs(pv) > 0.0)) return -(k + 1);
-    if (p != k) {
-      for (int j = t; j < d; j += kCoreThreads) {
-        const double x = A[(int64_t)k * d + j];
-        A[(int64_t)k * d + j] = A[(int64_t)p * d + j];
-        A[(int64_t)p * d + j] = x;
+    if (r == k && p != k) {
+#pragma unroll
+      for (int q = 0; q < kPanel; ++q) a[q] = prow[buf][q];
+    } else if (r == p && p != k) {
+#pragma unroll
+      for (int q = 0; q < kPanel; ++q) a[q] = krow[buf][q];
+    }
+    if (have && r > k) {
+      const double l = a[c] / pv;
+      a[c] = l;
+#pragma unroll
+      for (int q = 0; q < kPanel; ++q)
+        if (q > c) a[q] -= l * prow[buf][q];
+    }
+  }
+  if (have) {
+#pragma unroll
+    for (int c = 0; c < kPanel; ++c)
+      if (c < nb) A[(int64_t)r * d + k0 + c] = a[c];
+  }
+}
+
+constexpr int kLuCols = 64;
+
+__global__ __launch_bounds__(256) void lu_update_kernel(int d, double* A, int k0, const int32_t* __restrict__ piv,
+                                                        const int32_t* __restrict__ info) {
+  __shared__ double L11[kPanel][kPanel];
+  __shared__ double U12[kPanel][kLuCols];
+  __shared__ double L21[64][kPanel];
+  if (*info != 0) return;
+  const int t = threadIdx.x;
+  const int nb = min(kPanel, d - k0);
+  const int kend = k0 + nb;
+  // column blocks: left of the panel first, then right of it
+  const int nleft = (k0 + kLuCols - 1) / kLuCols;
+  int c0;
+  bool right;
+  if ((int)blockIdx.x < nleft) {
+    c0 = blockIdx.x * kLuCols;
+    right = false;
+  } else {
+    c0 = kend + (blockIdx.x - nleft) * kLuCols;
+    right = true;
+  }
+  const int cend = right ? min(c0 + kLuCols, d) : min(c0 + kLuCols, k0);
+  const int cl = t & (kLuCols - 1);
+  const int col = c0 + cl;
+  const bool col_ok = col < cend;
+  // row exchanges of this panel, in order
+  if (t < kLuCols && col_ok) {
+    for (int k = k0; k < kend; ++k) {
+      const int p = piv[k];
+      if (p != k) {
+        const double x = A[(int64_t)k * d + col];
+        A[(int64_t)k * d + col] = A[(int64_t)p * d + col];
+        A[(int64_t)p * d + col] = x;
+      }
+    }
+  }
+  if (!right) return;
+  for (int e = t; e < kPanel * kPanel; e += 256) {
+    const int i = e / kPanel, j = e % kPanel;
+    L11[i][j] = (i < nb && j < nb) ? A[(int64_t)(k0 + i) * d + k0 + j] : 0.0;
+  }
+  __syncthreads();
+  // U12 = L11^{-1} A12 (unit lower), one column per thread
+  if (t < kLuCols) {
+    double u[kPanel];
+#pragma unroll
+    for (int i = 0; i < kPanel; ++i) u[i] = (col_ok && i < nb) ? A[(int64_t)(k0 + i) * d + col] : 0.0;
+#pragma unroll
+    for (int i = 0; i < kPanel; ++i)
+#pragma unroll
+      for (int q = 0; q < kPanel; ++q)
+        if (q < i) u[i] -= L11[i][q] * u[q];
+#pragma unroll
+    for (int i = 0; i < kPanel; ++i) {
+      U12[i][t] = u[i];
+      if (col_ok && i < nb) A[(int64_t)(k0 + i) * d + col] = u[i];
+    }
+  }
+  __syncthreads();
+  // A22 -= L21 U12 over rows kend .. d-1 (4 row groups of the 64-row chunks)
+  const int rg = t >> 6;
+  for (int r0 = kend; r0 < d; r0 += 64) {
+    for (int e = t; e < 64 * kPanel; e += 256) {
+      const int i = e / kPanel, q = e % kPanel;
+      L21[i][q] = (r0 + i < d && q < nb) ? A[(int64_t)(r0 + i) * d + k0 + q] : 0.0;
+    }
+    __syncthreads();
+    if (col_ok) {
+      for (int i = rg; i < 64 && r0 + i < d; i += 4) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < kPanel; ++q) s += L21[i][q] * U12[q][cl];
+        A[(int64_t)(r0 + i) * d + col] -= s;
       }
     }
     __syncthreads();
-    const double inv = 1.0 / A[(int64_t)k * d + k];
-    for (int i = k + 1 + t; i < d; i += kCoreThreads) A[(int64_t)i * d + k] *= inv;
-    __syncthreads();
-    const int w = d - k - 1;
-    const int64_t cnt = (int64_t)w * w;
-    for (int64_t e = t; e < cnt; e += kCoreThreads) {
-      const int i = k + 1 + (int)(e / w);
-      const int j = k + 1 + (int)(e % w);
-      A[(int64_t)i * d + j] -= A[(int64_t)i * d + k] * A[(int64_t)k * d + j];
-    }
-    __syncthreads();
   }
-  return 0;
 }
 
-// Cholesky in place on the lower triangle of L (row-major). Returns 0 or k+1.
-__device__ int chol_inplace(double* L, int d) {
+// ---- blocked Cholesky of the lower triangle (panels of kPanel columns).
+__global__ __launch_bounds__(kCoreThreads) void chol_panel_kernel(int d, double* L, int k0, int32_t* info,
+                                                                  double* logdet) {
+  __shared__ double Lkk[kPanel][kPanel + 1];
+  __shared__ int bad;
+  if (*info != 0) return;
   const int t = threadIdx.x;
-  for (int k = 0; k < d; ++k) {
-    const double akk = L[(int64_t)k * d + k];
-    __syncthreads();
-    if (!(akk > 0.0)) return k + 1;
-    const double lkk = sqrt(akk);
-    const double inv = 1.0 / lkk;
-    for (int i = k + 1 + t; i < d; i += kCoreThreads) L[(int64_t)i * d + k] *= inv;
-    __syncthreads();
-    if (t == 0) L[(int64_t)k * d + k] = lkk;
-    const int w = d - k - 1;
-    const int64_t cnt = (int64_t)w * w;
-    for (int64_t e = t; e < cnt; e += kCoreThreads) {
-      const int i = k + 1 + (int)(e / w);
-      const int j = k + 1 + (int)(e % w);
-      if (j <= i) L[(int64_t)i * d + j] -= L[(int64_t)i * d + k] * L[(int64_t)j * d + k];
-    }
-    __syncthreads();
+  const int nb = min(kPanel, d - k0);
+  for (int e = t; e < kPanel * kPanel; e += kCoreThreads) {
+    const int i = e / kPanel, j = e % kPanel;
+    Lkk[i][j] = (i < nb && j < nb && j <= i) ? L[(int64_t)(k0 + i) * d + k0 + j] : 0.0;
   }
-  return 0;
-}
-
-// ---- forward core, three launches: LU(F); C = F^{-1} R^T (one wave per
-// right-hand side); symmetrise + shift + Cholesky + log-determinant.
-
-__global__ __launch_bounds__(kCoreThreads) void lu_kernel(int d, const double* __restrict__ F, double* Flu,
-                                                          int32_t* piv, int32_t* info, double* logdet) {
-  __shared__ double redv[kCoreWaves];
-  __shared__ int redi[kCoreWaves];
-  const int t = threadIdx.x;
-  const int64_t dd = (int64_t)d * d;
-  for (int64_t e = t; e < dd; e += kCoreThreads) Flu[e] = F[e];
+  if (t == 0) bad = 0;
   __syncthreads();
-  const int lu = lu_inplace(Flu, piv, d, redv, redi);
-  if (t == 0) {
-    *info = lu;
-    if (lu != 0) *logdet = __builtin_nan("");
+  // unblocked Cholesky of the diagonal block by the first wave
+  if (t < 64) {
+    for (int c = 0; c < nb; ++c) {
+      double dc = Lkk[c][c];
+      for (int q = 0; q < c; ++q) dc -= Lkk[c][q] * Lkk[c][q];
+      if (!(dc > 0.0)) {
+        if (t == 0) bad = k0 + c + 1;
+        break;
+      }
+      const double lcc = sqrt(dc);
+      __builtin_amdgcn_wave_barrier();
+      if (t > c && t < nb) {
+        double x = Lkk[t][c];
+        for (int q = 0; q < c; ++q) x -= Lkk[t][q] * Lkk[c][q];
+        Lkk[t][c] = x / lcc;
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (t == 0) Lkk[c][c] = lcc;
+      __builtin_amdgcn_wave_barrier();
+    }
   }
+  __syncthreads();
+  if (bad != 0) {
+    if (t == 0) {
+      *info = bad;
+      *logdet = __builtin_nan("");
+    }
+    return;
+  }
+  for (int e = t; e < kPanel * kPanel; e += kCoreThreads) {
+    const int i = e / kPanel, j = e % kPanel;
+    if (i < nb && j < nb && j <= i) L[(int64_t)(k0 + i) * d + k0 + j] = Lkk[i][j];
+  }
+  // rows below: L[i, panel] = A[i, panel] Lkk^{-T}
+  for (int i = k0 + nb + t; i < d; i += kCoreThreads) {
+    double y[kPanel];
+#pragma unroll
+    for (int q = 0; q < kPanel; ++q) y[q] = (q < nb) ? L[(int64_t)i * d + k0 + q] : 0.0;
+#pragma unroll
+    for (int q = 0; q < kPanel; ++q) {
+      if (q < nb) {
+        double x = y[q];
+#pragma unroll
+        for (int p = 0; p < kPanel; ++p)
+          if (p < q) x -= y[p] * Lkk[q][p];
+        y[q] = x / Lkk[q][q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kPanel; ++q)
+      if (q < nb) L[(int64_t)i * d + k0 + q] = y[q];
+  }
+}
+
+// lower-triangle update A[i][j] -= sum_q L[i][k0+q] L[j][k0+q], k0+nb <= j <= i < d,
+// one workgroup per 64 x 64 tile (tile row >= tile column).
+__global__ __launch_bounds__(256) void chol_update_kernel(int d, double* L, int k0, const int32_t* __restrict__ info) {
+  __shared__ double Li[64][kPanel + 1];
+  __shared__ double Lj[64][kPanel + 1];
+  if (*info != 0) return;
+  const int nb = min(kPanel, d - k0);
+  const int base = k0 + nb;
+  // decode the lower-triangular tile index
+  int ti = 0;
+  int rem = blockIdx.x;
+  while (rem > ti) {
+    rem -= ti + 1;
+    ++ti;
+  }
+  const int tj = rem;
+  const int i0 = base + ti * 64, j0 = base + tj * 64;
+  const int t = threadIdx.x;
+  for (int e = t; e < 64 * kPanel; e += 256) {
+    const int r = e / kPanel, q = e % kPanel;
+    Li[r][q] = (i0 + r < d && q < nb) ? L[(int64_t)(i0 + r) * d + k0 + q] : 0.0;
+    Lj[r][q] = (j0 + r < d && q < nb) ? L[(int64_t)(j0 + r) * d + k0 + q] : 0.0;
+  }
+  __syncthreads();
+  const int cj = t & 63;
+  const int j = j0 + cj;
+  for (int r = t >> 6; r < 64; r += 4) {
+    const int i = i0 + r;
+    if (i < d && j < d && j <= i) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < kPanel; ++q) s += Li[r][q] * Lj[cj][q];
+      L[(int64_t)i * d + j] -= s;
+    }
+  }
+}
+
+__global__ void shift_lower_kernel(int d, double sigma2, double nu, double* C, double* L,
+                                   const int32_t* __restrict__ info) {
+  if (*info != 0) return;
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)d * d) return;
+  const int i = (int)(e / d), j = (int)(e % d);
+  // symmetrise C (read both halves, each thread writes its own entry), lower part of S into L
+  const double s = 0.5 * (C[e] + C[(int64_t)j * d + i]);
+  L[e] = (j <= i) ? s + (i == j ? sigma2 - nu : 0.0) : 0.0;
+}
+
+// C <- (C + C^T) / 2 in place (one thread per pair i < j).
+__global__ void sym_kernel(int d, double* C, const int32_t* __restrict__ info) {
+  if (*info != 0) return;
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)d * d) return;
+  const int i = (int)(e / d), j = (int)(e % d);
+  if (i < j) {
+    const double s = 0.5 * (C[e] + C[(int64_t)j * d + i]);
+    C[e] = s;
+    C[(int64_t)j * d + i] = s;
+  }
+}
+
+__global__ __launch_bounds__(kCoreThreads) void logdet_kernel(int64_t n, int d, double sigma2, const double* L,
+                                                              double* logdet, const int32_t* __restrict__ info) {
+  __shared__ double red[kCoreWaves];
+  if (*info != 0) return;
+  double part = 0.0;
+  for (int k = threadIdx.x; k < d; k += kCoreThreads) part += log(L[(int64_t)k * d + k]);
+  const double s = block_sum(part, red);
+  if (threadIdx.x == 0) *logdet = (double)(n - d) * log(sigma2) + 2.0 * s;
+}
+
+__global__ void init_info_kernel(const double* __restrict__ F, double* Flu, int64_t count, int32_t* info) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < count) Flu[e] = F[e];
+  if (e == 0) *info = 0;
 }
 
 // Solve in place, for every column c of X (d x nrhs, leading dimension ldx):
-//   mode 0: X <- A^{-1} X with A = P L U from lu_inplace (pivots applied first);
+//   mode 0: X <- A^{-1} X with A = P L U from the blocked LU (pivots applied first);
 //   mode 1: X <- S^{-1} X with S = L L^T (lower Cholesky factor);
 //   mode 2: as 0, with the right-hand side read as B[c][i] = src[c * d + i]
 //           (i.e. the solve of A X = src^T), written to X.
@@ -246,50 +456,31 @@ hipError_t launch_solve_cols(hipStream_t st, int mode, int d, int nrhs, const do
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(kCoreThreads) void chol_kernel(int64_t n, int d, double sigma2, double nu, double* C,
-                                                            double* L, double* logdet, int32_t* info) {
-  __shared__ double red[kCoreWaves];
-  if (*info != 0) return;
-  const int t = threadIdx.x;
-  const int64_t dd = (int64_t)d * d;
-  const double shift = sigma2 - nu;
-  for (int64_t e = t; e < dd; e += kCoreThreads) {
-    const int i = (int)(e / d), j = (int)(e % d);
-    if (i < j) {
-      const double s = 0.5 * (C[e] + C[(int64_t)j * d + i]);
-      C[e] = s;
-      C[(int64_t)j * d + i] = s;
-    }
-  }
-  __syncthreads();
-  for (int64_t e = t; e < dd; e += kCoreThreads) {
-    const int i = (int)(e / d), j = (int)(e % d);
-    L[e] = (j <= i) ? C[e] + (i == j ? shift : 0.0) : 0.0;
-  }
-  __syncthreads();
-  const int ch = chol_inplace(L, d);
-  if (ch != 0) {
-    if (t == 0) {
-      *info = ch;
-      *logdet = __builtin_nan("");
-    }
-    return;
-  }
-  double part = 0.0;
-  for (int k = t; k < d; k += kCoreThreads) part += log(L[(int64_t)k * d + k]);
-  const double s = block_sum(part, red);
-  if (t == 0) *logdet = (double)(n - d) * log(sigma2) + 2.0 * s;
-}
-
 hipError_t launch_core(hipStream_t st, int64_t n, int d, const double* F, const double* R, double sigma2, double nu,
                        double* Flu, int32_t* piv, double* C, double* L, double* logdet, int32_t* info) {
-  hipLaunchKernelGGL(lu_kernel, dim3(1), dim3(kCoreThreads), 0, st, d, F, Flu, piv, info, logdet);
+  const int64_t dd = (int64_t)d * d;
+  const unsigned ddb = (unsigned)((dd + 255) / 256);
+  hipLaunchKernelGGL(init_info_kernel, dim3(ddb), dim3(256), 0, st, F, Flu, dd, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  for (int k0 = 0; k0 < d; k0 += kPanel) {
+    hipLaunchKernelGGL(lu_panel_kernel, dim3(1), dim3(kCoreThreads), 0, st, d, Flu, k0, piv, info, logdet);
+    const int kend = min(k0 + kPanel, d);
+    const int nblk = (k0 + kLuCols - 1) / kLuCols + (d - kend + kLuCols - 1) / kLuCols;
+    if (nblk > 0) hipLaunchKernelGGL(lu_update_kernel, dim3(nblk), dim3(256), 0, st, d, Flu, k0, piv, info);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   // C = F^{-1} R^T: column c of R^T is row c of R
-  e = launch_solve_cols(st, 2, d, d, Flu, piv, R, C, d, info);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(kCoreThreads), 0, st, n, d, sigma2, nu, C, L, logdet, info);
+  if ((e = launch_solve_cols(st, 2, d, d, Flu, piv, R, C, d, info)) != hipSuccess) return e;
+  hipLaunchKernelGGL(shift_lower_kernel, dim3(ddb), dim3(256), 0, st, d, sigma2, nu, C, L, info);
+  hipLaunchKernelGGL(sym_kernel, dim3(ddb), dim3(256), 0, st, d, C, info);
+  for (int k0 = 0; k0 < d; k0 += kPanel) {
+    hipLaunchKernelGGL(chol_panel_kernel, dim3(1), dim3(kCoreThreads), 0, st, d, L, k0, info, logdet);
+    const int base = min(k0 + kPanel, d);
+    const int nt = (d - base + 63) / 64;
+    if (nt > 0) hipLaunchKernelGGL(chol_update_kernel, dim3(nt * (nt + 1) / 2), dim3(256), 0, st, d, L, k0, info);
+  }
+  hipLaunchKernelGGL(logdet_kernel, dim3(1), dim3(kCoreThreads), 0, st, n, d, sigma2, L, logdet, info);
   return hipGetLastError();
 }
 

@@ -25,28 +25,34 @@ constexpr int kPanelWaves = kPanelThreads / 64;
 constexpr int kUpdThreads = 256;
 constexpr int kUpdCols = 64;
 
+// Sum of NV values over the 1024-thread block; every thread gets the totals.
+// Wave sums go to one of two LDS buffers (alternating between calls, so one
+// barrier per call suffices) and every thread adds the 16 wave partials in
+// the same order.
 template <typename T, int NV>
-__device__ __forceinline__ void block_sum_vec(T (&v)[NV], int nvalid, T* red, T* res) {
+__device__ __forceinline__ void block_sum_vec(T (&v)[NV], int nvalid, T* red, int& parity) {
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
+  T* buf = red + parity * (kPanelWaves * NV);
+  parity ^= 1;
 #pragma unroll
   for (int i = 0; i < NV; ++i)
     if (i < nvalid) v[i] = wave_sum(v[i]);
   if (lane == 0) {
 #pragma unroll
     for (int i = 0; i < NV; ++i)
-      if (i < nvalid) red[w * NV + i] = v[i];
-  }
-  __syncthreads();
-  if ((int)threadIdx.x < nvalid) {
-    T s = 0;
-    for (int k = 0; k < kPanelWaves; ++k) s += red[k * NV + threadIdx.x];
-    res[threadIdx.x] = s;
+      if (i < nvalid) buf[w * NV + i] = v[i];
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < NV; ++i)
-    if (i < nvalid) v[i] = res[i];
+  for (int i = 0; i < NV; ++i) {
+    if (i < nvalid) {
+      T s = 0;
+#pragma unroll
+      for (int k = 0; k < kPanelWaves; ++k) s += buf[k * NV + i];
+      v[i] = s;
+    }
+  }
 }
 
 // Rows a panel touches. Plain mode: rows p0 .. m-1. Tree mode (tree_d = d > 0,
@@ -82,9 +88,9 @@ __global__ __launch_bounds__(kPanelThreads) void panel_factor_kernel(T* __restri
                                                                      int tree_d, T* __restrict__ tau_all,
                                                                      int64_t tau_bstride, T* __restrict__ tmat,
                                                                      int64_t t_bstride) {
-  __shared__ T red[kPanelWaves * NB];
-  __shared__ T res[NB];
-  __shared__ T s_alpha;
+  __shared__ T red1[2 * kPanelWaves];
+  __shared__ T redv[2 * kPanelWaves * NB];
+  __shared__ T s_alpha[NB];
   __shared__ T s_tau[NB];
   __shared__ T s_y[NB * NB];  // s_y[c * NB + c1] = (V^T v_c)[c1], c1 < c
   __shared__ T s_t[NB * NB];
@@ -95,6 +101,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_factor_kernel(T* __restri
   const RowMap rm = make_rowmap<NB>(m, p0, tree_d);
   const int rows = rm.nact;
   const int t = threadIdx.x;
+  int par1 = 0, parv = 0;
 
   T a[RPT][NB];
 #pragma unroll
@@ -113,10 +120,10 @@ __global__ __launch_bounds__(kPanelThreads) void panel_factor_kernel(T* __restri
       const int lr = t + k * kPanelThreads;
       if (lr > c && lr < rows) part[0] += a[k][c] * a[k][c];
     }
-    if (t == c) s_alpha = a[0][c];
-    block_sum_vec<T, 1>(part, 1, red, res);
+    if (t == c) s_alpha[c] = a[0][c];
+    block_sum_vec<T, 1>(part, 1, red1, par1);
     const T sigma = part[0];
-    const T alpha = s_alpha;
+    const T alpha = s_alpha[c];
     T tau, beta, scal;
     if (sigma == (T)0) {
       tau = 0;
@@ -155,7 +162,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_factor_kernel(T* __restri
           if (i != c) wv[i] += vk[k] * a[k][i];
       }
     }
-    block_sum_vec<T, NB>(wv, nbw, red, res);
+    block_sum_vec<T, NB>(wv, nbw, redv, parv);
     if (t == 0) {
       s_tau[c] = tau;
 #pragma unroll
@@ -202,8 +209,25 @@ __global__ __launch_bounds__(kPanelThreads) void panel_factor_kernel(T* __restri
 
 // B[rows, cols] <- (I - V T' V^T) B[rows, cols], T' = T^T (TRANS) or T, over the
 // rows of the panel's row map. V occupies columns [p0, p0 + NB) of Vmat (unit
-// diagonal, zeros above). V is staged through LDS in chunks of kApplyChunk rows.
+// diagonal, zeros above). A 256-thread workgroup owns 64 columns; each thread
+// owns 16 bytes of consecutive columns (CPT = 4 floats or 2 doubles) so every
+// load keeps a full 16-byte request in flight; row groups are combined by
+// cross-lane shuffles and the 4 wave partials in LDS. V is staged through LDS
+// in chunks of kApplyChunk rows.
 constexpr int kApplyChunk = 64;
+
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int n = 2;
+};
 
 template <typename T, int NB, bool TRANS>
 __global__ __launch_bounds__(kUpdThreads) void panel_apply_kernel(const T* Vmat, int64_t vstride, T* Bmat,
@@ -211,6 +235,11 @@ __global__ __launch_bounds__(kUpdThreads) void panel_apply_kernel(const T* Vmat,
                                                                   int nbatch, int ld, int p0, int nbw, int tree_d,
                                                                   int col_begin, int col_end,
                                                                   const T* __restrict__ tmat, int64_t t_bstride) {
+  using VT = typename Vec16<T>::type;
+  constexpr int CPT = Vec16<T>::n;         // columns per thread
+  constexpr int TPR = kUpdCols / CPT;      // threads per row
+  constexpr int RG = kUpdThreads / TPR;    // row groups
+  constexpr int RGW = 64 / TPR;            // row groups per wave
   __shared__ T vch[kApplyChunk][NB];
   __shared__ T red[4][NB][kUpdCols];
   __shared__ T wsh[NB][kUpdCols];
@@ -223,11 +252,14 @@ __global__ __launch_bounds__(kUpdThreads) void panel_apply_kernel(const T* Vmat,
   const RowMap rm = make_rowmap<NB>(m, p0, tree_d);
   const int nact = rm.nact;
   const int t = threadIdx.x;
-  const int cl = t & (kUpdCols - 1);
-  const int rg = wave_uniform(t >> 6);
-  const int col = col_begin + blockIdx.x * kUpdCols + cl;
-  const bool col_ok = col < col_end;
-  const int colc = col_ok ? col : col_begin;  // in-bounds column for loads
+  const int w = t >> 6;
+  const int lane = t & 63;
+  const int tc = t % TPR;
+  const int rg = t / TPR;
+  const int cbase = col_begin + blockIdx.x * kUpdCols;
+  const int col0 = cbase + tc * CPT;
+  // vector access needs every column of the vector present and 16-byte alignment
+  const bool vec_ok = (col0 + CPT <= col_end) && (((int64_t)ld * sizeof(T)) % 16 == 0) && (col0 % CPT == 0);
 
   if (t < NB * NB) Ts[t] = tmat[(int64_t)b * t_bstride + t];
 
@@ -245,61 +277,106 @@ __global__ __launch_bounds__(kUpdThreads) void panel_apply_kernel(const T* Vmat,
       vch[r][i] = val;
     }
   };
-
-  T acc[NB];
+  auto load_row = [&](int ci, T (&x)[CPT]) {
+    const T* src = B + (int64_t)rm.row(ci) * ld + col0;
+    if (vec_ok) {
+      const VT v = *reinterpret_cast<const VT*>(src);
+      __builtin_memcpy(&x[0], &v, sizeof(VT));
+    } else {
 #pragma unroll
-  for (int i = 0; i < NB; ++i) acc[i] = 0;
+      for (int q = 0; q < CPT; ++q) x[q] = (col0 + q < col_end) ? src[q] : (T)0;
+    }
+  };
+
+  T acc[NB][CPT];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) acc[i][q] = 0;
   for (int c0 = 0; c0 < nact; c0 += kApplyChunk) {
     stage(c0);
     __syncthreads();
+    const int rend = min(kApplyChunk, nact - c0);
 #pragma unroll 4
-    for (int r = rg; r < kApplyChunk; r += 4) {
-      const int ci = c0 + r;
-      const T x = (ci < nact) ? B[(int64_t)rm.row(ci < nact ? ci : 0) * ld + colc] : (T)0;
+    for (int r = rg; r < rend; r += RG) {
+      T x[CPT];
+      load_row(c0 + r, x);
 #pragma unroll
-      for (int i = 0; i < NB; ++i) acc[i] += vch[r][i] * x;
+      for (int i = 0; i < NB; ++i) {
+        const T vi = vch[r][i];
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) acc[i][q] += vi * x[q];
+      }
     }
     __syncthreads();
   }
+  // combine the row groups of each wave (lanes tc, tc + TPR, ...), then the waves
 #pragma unroll
-  for (int i = 0; i < NB; ++i) red[rg][i][cl] = acc[i];
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      T v = acc[i][q];
+#pragma unroll
+      for (int off = TPR; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+      acc[i][q] = v;
+    }
+  if (lane < TPR) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) red[w][i][tc * CPT + q] = acc[i][q];
+  }
   __syncthreads();
   if (t < kUpdCols) {
-    T w[NB];
+    T wv[NB];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) w[i] = red[0][i][t] + red[1][i][t] + red[2][i][t] + red[3][i][t];
+    for (int i = 0; i < NB; ++i) wv[i] = red[0][i][t] + red[1][i][t] + red[2][i][t] + red[3][i][t];
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      T s = 0;
+      T sum = 0;
       if (TRANS) {
         // (T^T w)_i = sum_{k <= i} T[k][i] w_k
 #pragma unroll
         for (int k = 0; k < NB; ++k)
-          if (k <= i) s += Ts[k * NB + i] * w[k];
+          if (k <= i) sum += Ts[k * NB + i] * wv[k];
       } else {
         // (T w)_i = sum_{k >= i} T[i][k] w_k
 #pragma unroll
         for (int k = 0; k < NB; ++k)
-          if (k >= i) s += Ts[i * NB + k] * w[k];
+          if (k >= i) sum += Ts[i * NB + k] * wv[k];
       }
-      wsh[i][t] = s;
+      wsh[i][t] = sum;
     }
   }
   __syncthreads();
-  T wl[NB];
+  T wl[NB][CPT];
 #pragma unroll
-  for (int i = 0; i < NB; ++i) wl[i] = wsh[i][cl];
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) wl[i][q] = wsh[i][tc * CPT + q];
   for (int c0 = 0; c0 < nact; c0 += kApplyChunk) {
     stage(c0);
     __syncthreads();
+    const int rend = min(kApplyChunk, nact - c0);
 #pragma unroll 4
-    for (int r = rg; r < kApplyChunk; r += 4) {
-      const int ci = c0 + r;
-      if (ci < nact && col_ok) {
-        T s = 0;
+    for (int r = rg; r < rend; r += RG) {
+      T x[CPT];
+      load_row(c0 + r, x);
 #pragma unroll
-        for (int i = 0; i < NB; ++i) s += vch[r][i] * wl[i];
-        B[(int64_t)rm.row(ci) * ld + col] -= s;
+      for (int i = 0; i < NB; ++i) {
+        const T vi = vch[r][i];
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) x[q] -= vi * wl[i][q];
+      }
+      T* dst = B + (int64_t)rm.row(c0 + r) * ld + col0;
+      if (vec_ok) {
+        VT v;
+        __builtin_memcpy(&v, &x[0], sizeof(VT));
+        *reinterpret_cast<VT*>(dst) = v;
+      } else {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q)
+          if (col0 + q < col_end) dst[q] = x[q];
       }
     }
     __syncthreads();
