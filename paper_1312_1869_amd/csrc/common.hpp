@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "lrinv.h"
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
@@ -139,6 +141,18 @@ __device__ __forceinline__ T wave_sum(T v) {
 }
 
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Calls f(std::integral_constant<int, I>{}) for I = B .. E-1, expanded at
+// compile time, so register arrays indexed by I inside f stay in registers.
+// (#pragma unroll may be declined for large bodies, and a register array
+// indexed by a loop variable then lives in scratch memory.)
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(static_cast<F&&>(f));
+  }
+}
 
 // Row (within a 16 x 16 output fragment) of accumulator register i for a lane
 // in k-group g = lane / 16 (the column is lane % 16). The float32 16x16x4 and

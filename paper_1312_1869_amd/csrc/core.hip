@@ -87,7 +87,11 @@ __global__ __launch_bounds__(kCoreThreads) void lu_panel_kernel(int d, double* A
 #pragma unroll
   for (int c = 0; c < kPanel; ++c) a[c] = (have && c < nb) ? A[(int64_t)r * d + k0 + c] : 0.0;
   int par = 0;
-  for (int c = 0; c < nb; ++c) {
+  bool ok = true;  // uniform over the block
+  // expanded at compile time so every register-array index is a constant
+  static_for<0, kPanel>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    if (!ok || c >= nb) return;
     const int k = k0 + c;
     // candidate magnitude on rows >= k (NaN never wins)
     const double mag = (have && r >= k) ? fabs(a[c]) : -1.0;
@@ -109,6 +113,7 @@ __global__ __launch_bounds__(kCoreThreads) void lu_panel_kernel(int d, double* A
         *info = -(k + 1);
         *logdet = __builtin_nan("");
       }
+      ok = false;
       return;
     }
     if (t == 0) piv[k] = p;
@@ -126,7 +131,8 @@ __global__ __launch_bounds__(kCoreThreads) void lu_panel_kernel(int d, double* A
       for (int q = 0; q < kPanel; ++q)
         if (q > c) a[q] -= l * prow[buf][q];
     }
-  }
+  });
+  if (!ok) return;
   if (have) {
 #pragma unroll
     for (int c = 0; c < kPanel; ++c)
@@ -177,20 +183,13 @@ __global__ __launch_bounds__(256) void lu_update_kernel(int d, double* A, int k0
     L11[i][j] = (i < nb && j < nb) ? A[(int64_t)(k0 + i) * d + k0 + j] : 0.0;
   }
   __syncthreads();
-  // U12 = L11^{-1} A12 (unit lower), one column per thread
+  // U12 = L11^{-1} A12 (unit lower), one column per thread, solved in LDS
   if (t < kLuCols) {
-    double u[kPanel];
-#pragma unroll
-    for (int i = 0; i < kPanel; ++i) u[i] = (col_ok && i < nb) ? A[(int64_t)(k0 + i) * d + col] : 0.0;
-#pragma unroll
-    for (int i = 0; i < kPanel; ++i)
-#pragma unroll
-      for (int q = 0; q < kPanel; ++q)
-        if (q < i) u[i] -= L11[i][q] * u[q];
-#pragma unroll
     for (int i = 0; i < kPanel; ++i) {
-      U12[i][t] = u[i];
-      if (col_ok && i < nb) A[(int64_t)(k0 + i) * d + col] = u[i];
+      double s = (col_ok && i < nb) ? A[(int64_t)(k0 + i) * d + col] : 0.0;
+      for (int q = 0; q < i; ++q) s -= L11[i][q] * U12[q][t];
+      U12[i][t] = s;
+      if (col_ok && i < nb) A[(int64_t)(k0 + i) * d + col] = s;
     }
   }
   __syncthreads();
@@ -261,21 +260,21 @@ __global__ __launch_bounds__(kCoreThreads) void chol_panel_kernel(int d, double*
     const int i = e / kPanel, j = e % kPanel;
     if (i < nb && j < nb && j <= i) L[(int64_t)(k0 + i) * d + k0 + j] = Lkk[i][j];
   }
-  // rows below: L[i, panel] = A[i, panel] Lkk^{-T}
-  for (int i = k0 + nb + t; i < d; i += kCoreThreads) {
+  // rows below: L[i, panel] = A[i, panel] Lkk^{-T} (one row per thread: d <= kCoreThreads)
+  const int i = k0 + nb + t;
+  if (i < d) {
     double y[kPanel];
 #pragma unroll
     for (int q = 0; q < kPanel; ++q) y[q] = (q < nb) ? L[(int64_t)i * d + k0 + q] : 0.0;
-#pragma unroll
-    for (int q = 0; q < kPanel; ++q) {
+    static_for<0, kPanel>([&](auto qq) {
+      constexpr int q = decltype(qq)::value;
       if (q < nb) {
         double x = y[q];
 #pragma unroll
-        for (int p = 0; p < kPanel; ++p)
-          if (p < q) x -= y[p] * Lkk[q][p];
+        for (int p = 0; p < q; ++p) x -= y[p] * Lkk[q][p];
         y[q] = x / Lkk[q][q];
       }
-    }
+    });
 #pragma unroll
     for (int q = 0; q < kPanel; ++q)
       if (q < nb) L[(int64_t)i * d + k0 + q] = y[q];

@@ -20,39 +20,36 @@
 
 namespace lr {
 
-constexpr int kPanelThreads = 1024;
-constexpr int kPanelWaves = kPanelThreads / 64;
 constexpr int kUpdThreads = 256;
 constexpr int kUpdCols = 64;
 
-// Sum of NV values over the 1024-thread block; every thread gets the totals.
-// Wave sums go to one of two LDS buffers (alternating between calls, so one
-// barrier per call suffices) and every thread adds the 16 wave partials in
-// the same order.
-template <typename T, int NV>
-__device__ __forceinline__ void block_sum_vec(T (&v)[NV], int nvalid, T* red, int& parity) {
+// Sum of NV values over the TPB-thread block; every thread gets the totals.
+// Each wave reduces with DPP moves, the first wave adds the wave partials in a
+// fixed order, and every thread reads the NV totals (two barriers).
+template <typename T, int NV, int TPB>
+__device__ __forceinline__ void block_sum_vec(T (&v)[NV], int nvalid, T* red, T* res) {
+  constexpr int NW = TPB / 64;
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  T* buf = red + parity * (kPanelWaves * NV);
-  parity ^= 1;
 #pragma unroll
   for (int i = 0; i < NV; ++i)
     if (i < nvalid) v[i] = wave_sum(v[i]);
   if (lane == 0) {
 #pragma unroll
     for (int i = 0; i < NV; ++i)
-      if (i < nvalid) buf[w * NV + i] = v[i];
+      if (i < nvalid) red[w * NV + i] = v[i];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nvalid) {
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) s += red[k * NV + threadIdx.x];
+    res[threadIdx.x] = s;
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    if (i < nvalid) {
-      T s = 0;
-#pragma unroll
-      for (int k = 0; k < kPanelWaves; ++k) s += buf[k * NV + i];
-      v[i] = s;
-    }
-  }
+  for (int i = 0; i < NV; ++i)
+    if (i < nvalid) v[i] = res[i];
 }
 
 // Rows a panel touches. Plain mode: rows p0 .. m-1. Tree mode (tree_d = d > 0,
@@ -82,14 +79,14 @@ __device__ __forceinline__ RowMap make_rowmap(int m, int p0, int tree_d) {
 }
 
 // Factor columns [p0, p0 + nbw) of every matrix in the batch.
-template <typename T, int RPT, int NB>
-__global__ __launch_bounds__(kPanelThreads) void panel_factor_kernel(T* __restrict__ A, int64_t bstride, int m_full,
+template <typename T, int RPT, int NB, int TPB>
+__global__ __launch_bounds__(TPB) void panel_factor_kernel(T* __restrict__ A, int64_t bstride, int m_full,
                                                                      int m_last, int nbatch, int ld, int p0, int nbw,
                                                                      int tree_d, T* __restrict__ tau_all,
                                                                      int64_t tau_bstride, T* __restrict__ tmat,
                                                                      int64_t t_bstride) {
-  __shared__ T red1[2 * kPanelWaves];
-  __shared__ T redv[2 * kPanelWaves * NB];
+  __shared__ T red[(TPB / 64) * NB];
+  __shared__ T res[NB];
   __shared__ T s_alpha[NB];
   __shared__ T s_tau[NB];
   __shared__ T s_y[NB * NB];  // s_y[c * NB + c1] = (V^T v_c)[c1], c1 < c
@@ -101,27 +98,30 @@ __global__ __launch_bounds__(kPanelThreads) void panel_factor_kernel(T* __restri
   const RowMap rm = make_rowmap<NB>(m, p0, tree_d);
   const int rows = rm.nact;
   const int t = threadIdx.x;
-  int par1 = 0, parv = 0;
 
   T a[RPT][NB];
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
-    const int lr = t + k * kPanelThreads;
+    const int lr = t + k * TPB;
     const int64_t roff = (lr < rows) ? (int64_t)rm.row(lr) * ld + p0 : 0;
 #pragma unroll
     for (int c = 0; c < NB; ++c) a[k][c] = (lr < rows && c < nbw) ? M[roff + c] : (T)0;
   }
 
-  for (int c = 0; c < nbw; ++c) {
+  // Expanded at compile time so every register-array index is a constant.
+  // Columns c >= nbw are zero: their reflector is the identity (tau = 0) and
+  // changes nothing, so all NB columns are processed.
+  static_for<0, NB>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
     // sigma = |x below the diagonal|^2 ; alpha = diagonal entry (compact row c)
     T part[1] = {0};
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
-      const int lr = t + k * kPanelThreads;
+      const int lr = t + k * TPB;
       if (lr > c && lr < rows) part[0] += a[k][c] * a[k][c];
     }
     if (t == c) s_alpha[c] = a[0][c];
-    block_sum_vec<T, 1>(part, 1, red1, par1);
+    block_sum_vec<T, 1, TPB>(part, 1, red, res);
     const T sigma = part[0];
     const T alpha = s_alpha[c];
     T tau, beta, scal;
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_factor_kernel(T* __restri
     T vk[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
-      const int lr = t + k * kPanelThreads;
+      const int lr = t + k * TPB;
       if (lr > c && lr < rows) {
         a[k][c] *= scal;
         vk[k] = a[k][c];
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_factor_kernel(T* __restri
     for (int i = 0; i < NB; ++i) wv[i] = 0;
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
-      const int lr = t + k * kPanelThreads;
+      const int lr = t + k * TPB;
       if (lr < rows && lr >= c) {
         // i > c: a[k][i] is x_i(lr); i < c: a[k][i] is the stored reflector
         // entry v_i(lr) (lr >= c > i), so both sums are v^T a[:, i].
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kPanelThreads) void panel_factor_kernel(T* __restri
           if (i != c) wv[i] += vk[k] * a[k][i];
       }
     }
-    block_sum_vec<T, NB>(wv, nbw, redv, parv);
+    block_sum_vec<T, NB, TPB>(wv, nbw, red, res);
     if (t == 0) {
       s_tau[c] = tau;
 #pragma unroll
@@ -175,13 +175,13 @@ __global__ __launch_bounds__(kPanelThreads) void panel_factor_kernel(T* __restri
       for (int i = 0; i < NB; ++i)
         if (i > c && i < nbw) a[k][i] -= tau * wv[i] * vk[k];
     }
-  }
+  });
   __syncthreads();
 
   // write the panel back (R on/above the diagonal, V below)
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
-    const int lr = t + k * kPanelThreads;
+    const int lr = t + k * TPB;
     if (lr < rows) {
       const int64_t roff = (int64_t)rm.row(lr) * ld + p0;
 #pragma unroll
@@ -426,14 +426,18 @@ __global__ void copy_kernel(const T* __restrict__ src, T* __restrict__ dst, int6
 
 // ------------------------------------------------------------------ host side
 
+// Panels are factored by kFactorThreads threads holding RPT rows each.
+constexpr int kFactorThreads = 512;
+
 static int pick_rpt(int m) {
-  if (m <= 1024) return 1;
-  if (m <= 2048) return 2;
-  if (m <= 4096) return 4;
-  return 8;
+  int r = 1;
+  while (r * kFactorThreads < m) r *= 2;
+  return r;
 }
 
-// Panel width: keep the register panel at <= 64 VGPRs per thread.
+// Panel width: keep the register panel at <= 64 32-bit words per thread, so
+// panel, reduction vector and temporaries fit the 256 VGPRs a 512-thread
+// workgroup allows without spilling.
 template <typename T>
 static int pick_nb(int rpt) {
   const int words = rpt * (int)(sizeof(T) / 4);
@@ -463,8 +467,8 @@ static QrShape qr_shape(int m_full, int m_last, int nbatch, int d, bool tree = f
 template <typename T, int RPT, int NB>
 static hipError_t launch_panel_factor_rn(hipStream_t st, T* A, int64_t bstride, const QrShape& s, int p0, int nbw,
                                          T* tau, T* tm) {
-  hipLaunchKernelGGL((panel_factor_kernel<T, RPT, NB>), dim3(s.nbatch), dim3(kPanelThreads), 0, st, A, bstride,
-                     s.m_full, s.m_last, s.nbatch, s.d, p0, nbw, s.tree_d, tau, (int64_t)s.d, tm,
+  hipLaunchKernelGGL((panel_factor_kernel<T, RPT, NB, kFactorThreads>), dim3(s.nbatch), dim3(kFactorThreads), 0, st,
+                     A, bstride, s.m_full, s.m_last, s.nbatch, s.d, p0, nbw, s.tree_d, tau, (int64_t)s.d, tm,
                      (int64_t)s.npanels * NB * NB);
   return hipGetLastError();
 }
@@ -476,7 +480,8 @@ static hipError_t launch_panel_factor_nb(hipStream_t st, int rpt, T* A, int64_t 
     case 1: return launch_panel_factor_rn<T, 1, NB>(st, A, bstride, s, p0, nbw, tau, tm);
     case 2: return launch_panel_factor_rn<T, 2, NB>(st, A, bstride, s, p0, nbw, tau, tm);
     case 4: return launch_panel_factor_rn<T, 4, NB>(st, A, bstride, s, p0, nbw, tau, tm);
-    default: return launch_panel_factor_rn<T, 8, NB>(st, A, bstride, s, p0, nbw, tau, tm);
+    case 8: return launch_panel_factor_rn<T, 8, NB>(st, A, bstride, s, p0, nbw, tau, tm);
+    default: return launch_panel_factor_rn<T, 16, NB>(st, A, bstride, s, p0, nbw, tau, tm);
   }
 }
 
