@@ -88,9 +88,10 @@ def read_traffic(kernel_key: str, src_hash: str):
         return None
 
 
-def cpu_baseline(w, x, om_np, budget_s: float = 12.0) -> dict:
+def cpu_baseline(w, x, om_np, sketch_flops: float, budget_s: float = 12.0) -> dict:
     """The FP64 oracle's sketch on a bounded sample of rows (the stage that holds
-    >99% of the algorithmic flops), rate scaled to TFLOP/s."""
+    >99% of the algorithmic flops), rate scaled to TFLOP/s with the same
+    algorithmic count per row as the GPU figure."""
     from threadpoolctl import threadpool_info
 
     from oracle import sketch as osk
@@ -104,10 +105,11 @@ def cpu_baseline(w, x, om_np, budget_s: float = 12.0) -> dict:
         osk.sketch_rows(x, rows, w.kernel, w.ell, w.s, om_np, k_round=None)
         rows_done += block
     el = time.perf_counter() - t0
-    flops = 2.0 * rows_done * w.n * w.d
+    flops = sketch_flops / w.n * rows_done
+    per_row = "2 n d" if w.omega == "gauss" else "n (log2 d + 1)"
     return {"value": flops / el / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
             "sample": f"FP64 oracle sketch Y[rows,:] = K_f[rows,:] Omega for {rows_done} random rows of the "
-                      f"n={w.n}, d={w.d} workload ({el:.1f} s; 2*rows*n*d flops)"}
+                      f"n={w.n}, d={w.d} workload ({el:.1f} s; {per_row} flops per row)"}
 
 
 def main() -> int:
@@ -119,6 +121,9 @@ def main() -> int:
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="only copy a buffer of this many MiB device to device (reference kernel for the HBM "
+                         "byte counters), then exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md for how it "
@@ -131,6 +136,13 @@ def main() -> int:
     from paper_1312_1869_amd import api
 
     dev = torch.device("cuda:0")
+    if args.calib_copy_mib > 0:
+        src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes": src.numel() * 4}), flush=True)
+        return 0
     w = W.WORKLOADS[args.workload]
     prec = w.prec
     rp = "f32" if prec == "bf16" else prec
@@ -192,7 +204,7 @@ def main() -> int:
     stage_ms = {k: float(np.mean(v)) for k, v in stages.items()}
     sk = stage_ms["sketch"]
 
-    src = source_hash("paper_1312_1869_amd/csrc/sketch.hip", "paper_1312_1869_amd/csrc/common.hpp")
+    src = source_hash("paper_1312_1869_amd/csrc/sketch_dense.hip", "paper_1312_1869_amd/csrc/common.hpp")
     if w.omega == "gauss":
         kernel_key = {"bf16": "sketch_dense_kernel<2", "f32": "sketch_dense_kernel<1",
                       "f64": "sketch_dense_kernel<0"}[prec]
@@ -238,7 +250,7 @@ def main() -> int:
                                "logdet_rel_diff_vs_fp64": ld_rel}
 
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(w, x, om_np)
+        cb = cpu_baseline(w, x, om_np, flops["sketch"])
         result["cpu_baseline"] = cb
 
     print(json.dumps(result), flush=True)
