@@ -106,8 +106,10 @@ TnOperand real_operand(const void* p, int64_t ld, int32_t prec) {
 
 // ---------------------------------------------------------------- sketch
 
+// prescaled points, padded with kPointPad zero rows so kernels may read a
+// whole step of columns past n without a bounds check
 size_t sketch_ws(int64_t n, int32_t D, int32_t prec) {
-  return al((size_t)n * point_stride(D) * real_size(prec));
+  return al((size_t)(n + kPointPad) * point_stride(D) * real_size(prec));
 }
 
 lr_status sketch_impl(hipStream_t st, int64_t n, int32_t D, const float* X, const lr_hyper* hyp,

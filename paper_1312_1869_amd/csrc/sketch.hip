@@ -19,11 +19,17 @@ namespace lr {
 
 // ------------------------------------------------------------------ prescale
 
+// Rows n .. n + kPointPad - 1 are written as zeros (padding for kernels that
+// read whole steps of columns).
 template <typename T>
 __global__ void prep_points_kernel(const float* __restrict__ X, int64_t n, int D, int PD, T scale,
                                    const int8_t* __restrict__ signs, T* __restrict__ out) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (j >= n) return;
+  if (j >= n + kPointPad) return;
+  if (j >= n) {
+    for (int t = 0; t < PD; ++t) out[j * PD + t] = (T)0;
+    return;
+  }
   for (int t = 0; t < PD - 1; ++t) out[j * PD + t] = (t < D) ? (T)X[j * D + t] * scale : (T)0;
   out[j * PD + PD - 1] = (signs != nullptr && signs[j] < 0) ? (T)-1 : (T)1;
 }
@@ -32,7 +38,7 @@ template <typename T>
 hipError_t launch_prep_points(hipStream_t st, const float* X, int64_t n, int D, int PD, double scale,
                               const int8_t* signs, T* out) {
   const int threads = 256;
-  const int64_t blocks = (n + threads - 1) / threads;
+  const int64_t blocks = (n + kPointPad + threads - 1) / threads;
   hipLaunchKernelGGL(prep_points_kernel<T>, dim3((unsigned)blocks), dim3(threads), 0, st, X, n, D, PD,
                      (T)scale, signs, out);
   return hipGetLastError();

@@ -180,20 +180,32 @@ __global__ __launch_bounds__(512, 1) void sketch_dense_kernel(
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[f][c][i] = 0;
 
+    // Points x_j of the 8 columns of K a wave evaluates in a step (wave
+    // uniform, so they live in scalar registers). Indices past n are clamped;
+    // those kernel values are masked in the ragged tail.
+    using PtsStep = Real[8][ND];
+    auto load_pts = [&](int64_t step, PtsStep& xj) {
+      const int64_t j0 = step * kDenseStep + 8 * gg;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t j = (j0 + e < n) ? j0 + e : n - 1;
+#pragma unroll
+        for (int t = 0; t < ND; ++t) xj[e][t] = pts[j * PD + t];
+      }
+    };
     TE gen[8];
     // Kernel values K[row0 + grow, j0 + e], j0 = step * 32 + 8 gg (FULL: j < n known).
-    auto generate = [&](int64_t step, auto full_tag) {
+    auto generate = [&](int64_t step, const PtsStep& xj, auto full_tag) {
       constexpr bool FULL = decltype(full_tag)::value;
       const int64_t j0 = step * kDenseStep + 8 * gg;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const int64_t j = j0 + e;
         Real val = 0;
-        if (FULL || j < n) {
+        if (FULL || j0 + e < n) {
           Real r2 = 0;
 #pragma unroll
           for (int t = 0; t < ND; ++t) {
-            const Real df = xi[t] - pts[j * PD + t];
+            const Real df = xi[t] - xj[e][t];
             r2 += df * df;
           }
           val = DERIV ? K::deriv(r2) : K::value(r2);
@@ -206,35 +218,37 @@ __global__ __launch_bounds__(512, 1) void sketch_dense_kernel(
 #pragma unroll
       for (int e = 0; e < 8; ++e) dst[e] = gen[e];
     };
-    // Omega columns of this wave; columns >= d read column 0 and are zeroed.
-    const typename Cfg::OmegaElem* ocol[WN];
+    // Omega columns of this wave: a wave-uniform base (column colw) and 32-bit
+    // per-lane element offsets of the WN fragments' columns. Columns >= d read
+    // column 0 and only feed accumulator columns that are never stored.
+    const typename Cfg::OmegaElem* obase = omt + (int64_t)(colw < d ? colw : 0) * ld;
+    uint32_t coff[WN];
     bool cok[WN];
 #pragma unroll
     for (int c = 0; c < WN; ++c) {
       const int col = colw + 16 * c + fl;
       cok[c] = col < d;
-      ocol[c] = omt + (int64_t)(cok[c] ? col : 0) * ld;
+      coff[c] = cok[c] ? (uint32_t)((int64_t)(16 * c + fl) * ld) : 0u;
     }
-    // One step: the 8 A fragments of step s come from LDS, the Omega fragments
-    // of step s were loaded during the previous step (those of step s + 1 are
-    // requested now), and the kernel tile of step s + 1 is evaluated on the
-    // vector ALUs interleaved with the 8 x WN matrix-core products of step s.
-    OmegaFrag<PREC> b[WN];
     auto load_b = [&](int64_t s, OmegaFrag<PREC> (&dst)[WN], auto full_tag) {
       constexpr bool FULL = decltype(full_tag)::value;
       const int64_t jb = s * kDenseStep + 8 * fg;
 #pragma unroll
       for (int c = 0; c < WN; ++c) {
         if (FULL) {
-          // columns >= d read column 0: their products land only in
-          // accumulator columns that are never stored
-          load_omega8<PREC>(ocol[c], jb, jb + 8, true, dst[c]);
+          load_omega8<PREC>(obase + coff[c], jb, jb + 8, true, dst[c]);
         } else {
-          load_omega8<PREC>(ocol[c], jb, n, cok[c], dst[c]);
+          load_omega8<PREC>(obase + coff[c], jb, n, cok[c], dst[c]);
         }
       }
     };
-    auto step_body = [&](int64_t s, auto full_tag) {
+    // One step s: the 8 A fragments come from LDS tile s, the Omega fragments
+    // b were requested during step s - 1 (those of step s + 1 go to bn now),
+    // the points of step s + 1 were loaded during step s - 1 (those of step
+    // s + 2 go to xjn now), and the kernel tile of step s + 1 is evaluated on
+    // the vector ALUs interleaved with the 8 x WN matrix-core products.
+    auto step_body = [&](int64_t s, OmegaFrag<PREC> (&b)[WN], OmegaFrag<PREC> (&bn)[WN], const PtsStep& xj,
+                         PtsStep& xjn, auto full_tag) {
       constexpr bool FULL = decltype(full_tag)::value;
       const int cur = (int)(s & 1);
       OmegaFrag<PREC> a[8];
@@ -245,37 +259,50 @@ __global__ __launch_bounds__(512, 1) void sketch_dense_kernel(
         for (int e = 0; e < 8; ++e) a[f].v[e] = src[e];
       }
       const bool has_next = FULL || s + 1 < nsteps;
-      OmegaFrag<PREC> bn[WN];
-      if (has_next) load_b(s + 1, bn, full_tag);
-      if (has_next) generate(s + 1, full_tag);
+      if (has_next) {
+        load_b(s + 1, bn, full_tag);
+        generate(s + 1, xj, full_tag);
+      }
 #pragma unroll
       for (int f = 0; f < 8; ++f)
 #pragma unroll
         for (int c = 0; c < WN; ++c) mfma_step<PREC>(acc[f][c], a[f], b[c]);
       if constexpr (PREC == LR_PREC_BF16 && FULL) {
-        // interleave: one matrix-core op, then up to four vector ALU ops
+        // interleave: one matrix-core op, then up to two vector ALU ops
 #pragma unroll
         for (int i = 0; i < 8 * WN; ++i) {
           __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-          __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+          __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
         }
       }
       if (has_next) store_gen(cur ^ 1);
-#pragma unroll
-      for (int c = 0; c < WN; ++c) b[c] = bn[c];
       __syncthreads();
+      // requested after the barrier's wait, so the step's LDS waits do not
+      // also wait for these scalar loads
+      if (s + 2 < nsteps) load_pts(s + 2, xjn);
     };
 
-    generate(0, std::false_type{});
+    OmegaFrag<PREC> bA[WN], bB[WN];
+    PtsStep xA, xB;
+    load_pts(0, xA);
+    generate(0, xA, std::false_type{});
     store_gen(0);
-    load_b(0, b, std::false_type{});
+    load_b(0, bA, std::false_type{});
+    if (nsteps > 1) load_pts(1, xA);
     __syncthreads();
 
-    // steps s with s + 1 < nfull have both tiles s and s + 1 inside [0, n)
+    // Steps in pairs with the operand registers alternating roles. A step s
+    // runs FULL when the tile it evaluates (s + 1) lies inside [0, n).
     const int64_t nfull = n / kDenseStep;
     int64_t s = 0;
-    for (; s + 1 < nfull; ++s) step_body(s, std::true_type{});
-    for (; s < nsteps; ++s) step_body(s, std::false_type{});
+    for (; s + 2 < nfull; s += 2) {
+      step_body(s, bA, bB, xA, xB, std::true_type{});
+      step_body(s + 1, bB, bA, xB, xA, std::true_type{});
+    }
+    for (; s < nsteps; s += 2) {
+      step_body(s, bA, bB, xA, xB, std::false_type{});
+      if (s + 1 < nsteps) step_body(s + 1, bB, bA, xB, xA, std::false_type{});
+    }
 
     const bool wave_active = colw < d;
     if (wave_active) {
@@ -297,6 +324,263 @@ __global__ __launch_bounds__(512, 1) void sketch_dense_kernel(
       }
     }
   }
+}
+
+// ------------------------------------------------------------------ bf16, one wave per SIMD
+//
+// sketch_bf16_kernel: the bf16 sketch with a 256-thread workgroup (4 waves,
+// one per SIMD, so each wave may hold 512 registers). A workgroup owns 128
+// rows x 64*WC columns of Y (WC <= 4); each wave keeps the accumulators of all
+// 128 rows x its 16*WC columns (in the accumulation registers). For d above
+// 64*WC the column blocks are separate workgroups, each evaluating the kernel
+// tiles of its rows again. Per step of 32
+// columns j of K:
+//   * every thread evaluates 16 kernel entries (one row, 16 consecutive j):
+//     its x_i is in registers, and x_j comes from a vector load of the 16
+//     points of the step (lane fl of each 16-lane row holds point fl), read
+//     back with a DPP row broadcast, so no scalar loads sit between the
+//     matrix-core operations;
+//   * the entries are rounded to bf16 and written to a double-buffered LDS
+//     tile in operand order; each wave reads the 8 row fragments of the tile
+//     and multiplies them with its WC Omega fragments (8 x WC products);
+//   * Omega fragments of step s + 1 are requested at the start of step s and
+//     the points of step s + 2 with them, in two alternating register sets.
+// The vector work of step s + 1 is interleaved with the products of step s.
+
+#ifndef LR_B16_WAVES
+#define LR_B16_WAVES 8
+#endif
+constexpr int kB16Waves = LR_B16_WAVES;
+
+template <int E>
+__device__ __forceinline__ float row_bcast(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x150 + E, 0xF, 0xF,
+                                                               false));
+}
+
+template <int NW, int KERNEL, int PD, int ND, int WC, bool DERIV>
+__global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __restrict__ pts,
+                                                                     const uint16_t* __restrict__ omt, int64_t ld,
+                                                                     int64_t n, int d, float scale_out, float nu,
+                                                                     float* __restrict__ Y, int nrb, int ncb) {
+  using K = KernelT<float, KERNEL>;
+  using Frag = OmegaFrag<LR_PREC_BF16>;
+  constexpr int BN = NW * 16 * WC;
+  constexpr int GPT = 64 / NW;  // kernel entries per thread per step (8 or 16)
+  constexpr int kValuPerMfma = (9 * GPT / (8 * WC)) > 2 ? (9 * GPT / (8 * WC)) : 2;
+  static_assert(NW == 4 || NW == 8, "4 or 8 waves");
+
+  __shared__ __align__(16) __bf16 tile[2][4 * kDenseRows * 8];  // [buf][k-group][row][8]
+
+  const int tid = threadIdx.x;
+  const int w = tid >> 6;
+  const int lane = tid & 63;
+  const int grow = (w & 1) * 64 + lane;  // generation: row of the tile
+  const int gg = wave_uniform(w >> 1);   // generation: j = GPT gg .. GPT gg + GPT - 1 of the step
+  const int fl = lane & 15;
+  const int fg = lane >> 4;
+  const int64_t nsteps = (n + kDenseStep - 1) / kDenseStep;
+  const int64_t nfull = n / kDenseStep;
+  const int nblk = nrb * ncb;
+
+  for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int rb = blk % nrb;
+    const int cb = blk / nrb;
+    const int64_t row0 = (int64_t)rb * kDenseRows;
+    const int colw = cb * BN + w * 16 * WC;
+
+    float xi[ND];
+    {
+      int64_t r = row0 + grow;
+      if (r >= n) r = n - 1;
+#pragma unroll
+      for (int t = 0; t < ND; ++t) xi[t] = pts[r * PD + t];
+    }
+
+    f32x4_t acc[8][WC];
+#pragma unroll
+    for (int f = 0; f < 8; ++f)
+#pragma unroll
+      for (int c = 0; c < WC; ++c)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[f][c][i] = 0.0f;
+
+    // x_j of j = 32 step + GPT gg + (fl mod GPT) (inside the zero-padded
+    // point array)
+    using Pts = float[ND];
+    auto load_pts = [&](int64_t step, Pts& p) {
+      const int64_t j = step * kDenseStep + GPT * gg + (fl & (GPT - 1));
+#pragma unroll
+      for (int t = 0; t < ND; ++t) p[t] = pts[j * PD + t];
+    };
+    __bf16 gen[GPT];
+    auto generate = [&](int64_t step, const Pts& p, auto full_tag) {
+      constexpr bool FULL = decltype(full_tag)::value;
+      const int64_t j0 = step * kDenseStep + GPT * gg;
+      static_for<0, GPT>([&](auto ee) {
+        constexpr int e = decltype(ee)::value;
+        float r2 = 0.0f;
+#pragma unroll
+        for (int t = 0; t < ND; ++t) {
+          const float df = row_bcast<e>(p[t]) - xi[t];
+          r2 = __builtin_fmaf(df, df, r2);
+        }
+        float val = DERIV ? K::deriv(r2) : K::value(r2);
+        if (!FULL && j0 + e >= n) val = 0.0f;
+        gen[e] = (__bf16)val;
+      });
+    };
+    auto store_gen = [&](int buf) {
+#pragma unroll
+      for (int u = 0; u < GPT / 8; ++u) {
+        __bf16* dst = &tile[buf][((GPT / 8 * gg + u) * kDenseRows + grow) * 8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) dst[e] = gen[8 * u + e];
+      }
+    };
+    // Omega columns of this wave: wave-uniform base (column colw) plus 32-bit
+    // lane offsets; columns >= d read column 0 and feed only accumulator
+    // columns that are never stored.
+    const uint16_t* obase = omt + (int64_t)(colw < d ? colw : 0) * ld;
+    uint32_t coff[WC];
+    bool cok[WC];
+#pragma unroll
+    for (int c = 0; c < WC; ++c) {
+      const int col = colw + 16 * c + fl;
+      cok[c] = col < d;
+      coff[c] = cok[c] ? (uint32_t)((int64_t)(16 * c + fl) * ld) : 0u;
+    }
+    // 8 consecutive j of a column in one 16-byte load (jb and ld are multiples
+    // of 8, so a load starting below ld stays inside the column); in the
+    // ragged tail the entries j >= n are cleared in registers.
+    auto load_b = [&](int64_t s, Frag (&dst)[WC], auto full_tag) {
+      constexpr bool FULL = decltype(full_tag)::value;
+      const int64_t jb = s * kDenseStep + 8 * fg;
+      uint32_t keep[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+      if (!FULL) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          keep[q] = (jb + 2 * q < n ? 0x0000FFFFu : 0u) | (jb + 2 * q + 1 < n ? 0xFFFF0000u : 0u);
+      }
+#pragma unroll
+      for (int c = 0; c < WC; ++c) {
+        uint4 raw = {0u, 0u, 0u, 0u};
+        if (FULL || jb < ld) raw = *reinterpret_cast<const uint4*>(obase + coff[c] + jb);
+        if (!FULL) {
+          raw.x &= keep[0];
+          raw.y &= keep[1];
+          raw.z &= keep[2];
+          raw.w &= keep[3];
+        }
+        __builtin_memcpy(&dst[c].v[0], &raw, 16);
+      }
+    };
+    // Step s: b holds Omega of step s, bl receives Omega of step s + 1
+    // (requested first thing, so nearly a whole step hides its latency), pg
+    // holds the points of step s + 1, pl receives those of step s + 2. FULL:
+    // step s + 1 lies inside [0, n).
+    auto step_body = [&](int64_t s, Frag (&b)[WC], Frag (&bl)[WC], const Pts& pg, Pts& pl, auto full_tag) {
+      constexpr bool FULL = decltype(full_tag)::value;
+      const int cur = (int)(s & 1);
+      const bool has_next = FULL || s + 1 < nsteps;
+      if (has_next) load_b(s + 1, bl, full_tag);
+      if (FULL || s + 2 < nsteps) load_pts(s + 2, pl);
+      Frag a[8];
+#pragma unroll
+      for (int f = 0; f < 8; ++f) {
+        const __bf16* src = &tile[cur][(fg * kDenseRows + 16 * f + fl) * 8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) a[f].v[e] = src[e];
+      }
+      if (has_next) generate(s + 1, pg, full_tag);
+#pragma unroll
+      for (int f = 0; f < 8; ++f)
+#pragma unroll
+        for (int c = 0; c < WC; ++c) mfma_step<LR_PREC_BF16>(acc[f][c], a[f], b[c]);
+      if constexpr (FULL) {
+        __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);  // the 8 LDS operand reads first
+#pragma unroll
+        for (int i = 0; i < 8 * WC; ++i) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x002, kValuPerMfma, 0);
+        }
+      }
+      if (has_next) store_gen(cur ^ 1);
+      __syncthreads();
+    };
+
+    Frag b0[WC], b1[WC];
+    Pts p0, p1;
+    load_pts(0, p0);
+    generate(0, p0, std::false_type{});
+    store_gen(0);
+    load_b(0, b0, std::false_type{});
+    load_pts(1, p1);
+    __syncthreads();
+
+    // pairs of steps with the register sets alternating roles
+    int64_t s = 0;
+    for (; s + 2 < nfull; s += 2) {
+      step_body(s, b0, b1, p1, p0, std::true_type{});
+      step_body(s + 1, b1, b0, p0, p1, std::true_type{});
+    }
+    for (; s < nsteps; s += 2) {
+      step_body(s, b0, b1, p1, p0, std::false_type{});
+      if (s + 1 < nsteps) step_body(s + 1, b1, b0, p0, p1, std::false_type{});
+    }
+
+#pragma unroll
+    for (int f = 0; f < 8; ++f) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t row = row0 + 16 * f + acc_row<f32x4_t>(fg, i);
+        if (row < n) {
+          float* yr = Y + row * d + colw + fl;
+#pragma unroll
+          for (int c = 0; c < WC; ++c)
+            if (cok[c]) yr[16 * c] = scale_out * acc[f][c][i];
+        }
+      }
+    }
+    if (!DERIV && nu != 0.0f) {  // + nu Omega (Y written by this thread above)
+      for (int c = 0; c < WC; ++c) {
+        if (!cok[c]) continue;
+        const int col = colw + 16 * c + fl;
+        for (int f = 0; f < 8; ++f)
+          for (int i = 0; i < 4; ++i) {
+            const int64_t row = row0 + 16 * f + acc_row<f32x4_t>(fg, i);
+            if (row < n) Y[row * d + col] += nu * omega_value<LR_PREC_BF16>(omt, ld, col, row);
+          }
+      }
+    }
+  }
+}
+
+template <int KERNEL, int PD, int ND, int WC, bool DERIV>
+static hipError_t launch_bf16_impl(hipStream_t st, const void* pts, const void* omt, int64_t ld, int64_t n, int d,
+                                   double scale_out, double nu, void* Y, int num_cu) {
+  constexpr int NW = kB16Waves;
+  constexpr int BN = NW * 16 * WC;
+  const int nrb = (int)((n + kDenseRows - 1) / kDenseRows);
+  const int ncb = (d + BN - 1) / BN;
+  int64_t blocks = (int64_t)nrb * ncb;
+  if (blocks > num_cu) blocks = num_cu;
+  hipLaunchKernelGGL((sketch_bf16_kernel<NW, KERNEL, PD, ND, WC, DERIV>), dim3((unsigned)blocks), dim3(NW * 64), 0,
+                     st, (const float*)pts, (const uint16_t*)omt, ld, n, d, (float)scale_out, (float)nu, (float*)Y,
+                     nrb, ncb);
+  return hipGetLastError();
+}
+
+template <int KERNEL, int PD, int ND, bool DERIV>
+static hipError_t launch_bf16_wc(hipStream_t st, const void* pts, const void* omt, int64_t ld, int64_t n, int d,
+                                 double so, double nu, void* Y, int num_cu) {
+  constexpr int cols_per_wc = kB16Waves * 16;
+  if (d <= cols_per_wc) return launch_bf16_impl<KERNEL, PD, ND, 1, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
+  if (d <= 2 * cols_per_wc)
+    return launch_bf16_impl<KERNEL, PD, ND, 2, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
+  // WC = 8 (512 accumulator registers per wave with 4 waves) does not fit the
+  // register file with the operands; larger d takes several column blocks
+  return launch_bf16_impl<KERNEL, PD, ND, 4, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
 }
 
 template <int PREC, int KERNEL, int PD, int ND, int WN, bool DERIV>
@@ -331,6 +615,16 @@ static hipError_t launch_dense_wn(hipStream_t st, const void* pts, const void* o
 template <int PREC, int KERNEL, bool DERIV>
 static hipError_t launch_dense_dim(hipStream_t st, int D, const void* pts, const void* omt, int64_t ld, int64_t n,
                                    int d, double so, double nu, void* Y, int num_cu) {
+  // bf16 with a point stride of 4 and 32-bit Omega lane offsets: one wave per SIMD
+  if constexpr (PREC == LR_PREC_BF16) {
+    if (D <= 3 && (int64_t)128 * ld < ((int64_t)1 << 32)) {
+      switch (D) {
+        case 1: return launch_bf16_wc<KERNEL, 4, 1, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
+        case 2: return launch_bf16_wc<KERNEL, 4, 2, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
+        default: return launch_bf16_wc<KERNEL, 4, 3, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
+      }
+    }
+  }
   switch (D) {
     case 1: return launch_dense_wn<PREC, KERNEL, 4, 1, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
     case 2: return launch_dense_wn<PREC, KERNEL, 4, 2, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
