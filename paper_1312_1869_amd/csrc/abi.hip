@@ -108,8 +108,16 @@ TnOperand real_operand(const void* p, int64_t ld, int32_t prec) {
 
 // prescaled points, padded with kPointPad zero rows so kernels may read a
 // whole step of columns past n without a bounds check
-size_t sketch_ws(int64_t n, int32_t D, int32_t prec) {
+size_t sketch_pts_bytes(int64_t n, int32_t D, int32_t prec) {
   return al((size_t)(n + kPointPad) * point_stride(D) * real_size(prec));
+}
+
+// prescaled points; for the bf16 sketch with D <= 3 also the fragment-order
+// copy of a Gaussian Omega
+size_t sketch_ws(int64_t n, int32_t D, int32_t d, int32_t prec) {
+  size_t b = sketch_pts_bytes(n, D, prec);
+  if (prec == LR_PREC_BF16 && D <= 3) b += al(omega_frag_bytes(n, d));
+  return b;
 }
 
 lr_status sketch_impl(hipStream_t st, int64_t n, int32_t D, const float* X, const lr_hyper* hyp,
@@ -139,10 +147,17 @@ lr_status sketch_impl(hipStream_t st, int64_t n, int32_t D, const float* X, cons
   } else {
     LR_HIP(launch_prep_points<float>(st, X, n, D, PD, scale, nullptr, static_cast<float*>(ws)));
   }
+  void* frag = nullptr;
+  if (prec == LR_PREC_BF16 && D <= 3) {
+    frag = static_cast<char*>(ws) + sketch_pts_bytes(n, D, prec);
+    LR_HIP(launch_omega_frag(st, omega->dense_t, omega->ld, n, d, frag));
+  }
   if (Y != nullptr)
-    LR_HIP(launch_sketch_dense(st, prec, hyp->kernel, D, ws, omega->dense_t, omega->ld, n, d, s2, nu, Y, false, ncu));
+    LR_HIP(launch_sketch_dense(st, prec, hyp->kernel, D, ws, omega->dense_t, omega->ld, n, d, s2, nu, Y, false, frag,
+                               ncu));
   if (Yp != nullptr)
-    LR_HIP(launch_sketch_dense(st, prec, hyp->kernel, D, ws, omega->dense_t, omega->ld, n, d, s2, 0.0, Yp, true, ncu));
+    LR_HIP(launch_sketch_dense(st, prec, hyp->kernel, D, ws, omega->dense_t, omega->ld, n, d, s2, 0.0, Yp, true, frag,
+                               ncu));
   return LR_OK;
 }
 
@@ -199,7 +214,7 @@ BackWs back_layout(int64_t n, int32_t D, int32_t d, int32_t m, int32_t prec) {
   w.off_yp = off;
   off = al(off + (size_t)n * d * rs);
   w.off_sk = off;
-  off = al(off + sketch_ws(n, D, prec));
+  off = al(off + sketch_ws(n, D, d, prec));
   size_t tn = tn_workspace(n, d, d);
   size_t t2 = tn_workspace(n, mm > d ? mm : d, mm > d ? mm : d);
   if (t2 > tn) tn = t2;
@@ -272,9 +287,8 @@ lr_status lr_check_srht_cols(const int32_t* cols, int32_t d, int64_t n) {
 }
 
 size_t lr_sketch_workspace_bytes(int64_t n, int32_t D, int32_t d, int32_t prec) {
-  (void)d;
   if (n < 1 || D < 1 || D > 15 || !valid_prec(prec)) return 0;
-  return sketch_ws(n, D, prec);
+  return sketch_ws(n, D, d, prec);
 }
 
 lr_status lr_sketch(void* stream, int64_t n, int32_t D, const float* X, const lr_hyper* hyp, const lr_omega* omega,
@@ -288,7 +302,7 @@ lr_status lr_sketch(void* stream, int64_t n, int32_t D, const float* X, const lr
   if ((s = check_hyper(hyp)) != LR_OK) return s;
   if ((s = check_omega(omega, n, omega->d, prec)) != LR_OK) return s;
   if (!is_fin(nu) || nu < 0.0) return LR_ERR_ARG;
-  if ((s = check_ws(sketch_ws(n, D, prec), ws, ws_bytes)) != LR_OK) return s;
+  if ((s = check_ws(sketch_ws(n, D, omega->d, prec), ws, ws_bytes)) != LR_OK) return s;
   return sketch_impl(static_cast<hipStream_t>(stream), n, D, X, hyp, omega, nu, prec, Y, Yprime, ws);
 }
 

@@ -16,7 +16,11 @@ hipError_t launch_sketch_srht(hipStream_t st, int kernel, int D, const T* pts, c
                               int d, double scale_out, double nu_c, T* Y, T* Yp, int num_cu);
 hipError_t launch_sketch_dense(hipStream_t st, int prec, int kernel, int D, const void* pts, const void* omt,
                                int64_t ld, int64_t n, int d, double scale_out, double nu, void* Y, bool deriv,
-                               int num_cu);
+                               const void* frag, int num_cu);
+// Omega (bf16, d x ld transposed) in matrix-core fragment order for the bf16
+// sketch with D <= 3; omega_frag_bytes gives the size of that copy.
+hipError_t launch_omega_frag(hipStream_t st, const void* omt, int64_t ld, int64_t n, int d, void* frag);
+size_t omega_frag_bytes(int64_t n, int d);
 
 // tsqr.hip
 size_t tsqr_workspace(int64_t n, int d, int leaf_rows, bool f64);

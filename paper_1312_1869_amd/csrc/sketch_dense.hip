@@ -326,31 +326,58 @@ __global__ __launch_bounds__(512, 1) void sketch_dense_kernel(
   }
 }
 
-// ------------------------------------------------------------------ bf16, one wave per SIMD
+// ------------------------------------------------------------------ bf16 on matrix cores
 //
-// sketch_bf16_kernel: the bf16 sketch with a 256-thread workgroup (4 waves,
-// one per SIMD, so each wave may hold 512 registers). A workgroup owns 128
-// rows x 64*WC columns of Y (WC <= 4); each wave keeps the accumulators of all
-// 128 rows x its 16*WC columns (in the accumulation registers). For d above
-// 64*WC the column blocks are separate workgroups, each evaluating the kernel
-// tiles of its rows again. Per step of 32
-// columns j of K:
-//   * every thread evaluates 16 kernel entries (one row, 16 consecutive j):
-//     its x_i is in registers, and x_j comes from a vector load of the 16
-//     points of the step (lane fl of each 16-lane row holds point fl), read
-//     back with a DPP row broadcast, so no scalar loads sit between the
-//     matrix-core operations;
+// Omega is first copied into matrix-core operand order (omega_frag_kernel):
+// for every 16-column group c16 and step s of 32 rows j, one 1 KB fragment
+// whose lane l = fl + 16 fg holds Omega[32 s + 8 fg .. + 7][16 c16 + fl] as 8
+// bf16. Rows j >= n and columns >= the padded width are zero, so the sketch
+// kernel reads every operand with one contiguous, unmasked 16-byte load per
+// lane and needs no ragged-tail handling (kernel values at j >= n meet zero
+// Omega rows).
+//
+// sketch_bf16_kernel: NW waves (NW * 64 threads, 8 waves = 2 per SIMD) own 128
+// rows x NW*16*WC columns of Y; each wave keeps the accumulators of the 128
+// rows x its 16*WC columns. Per step of 32 columns j of K:
+//   * every thread evaluates GPT = 64/NW kernel entries (one row, GPT
+//     consecutive j); its x_i is in registers, and x_j comes from one vector
+//     load per step (lane fl of each 16-lane row holds point fl mod GPT) read
+//     back with a DPP row broadcast;
 //   * the entries are rounded to bf16 and written to a double-buffered LDS
 //     tile in operand order; each wave reads the 8 row fragments of the tile
 //     and multiplies them with its WC Omega fragments (8 x WC products);
-//   * Omega fragments of step s + 1 are requested at the start of step s and
-//     the points of step s + 2 with them, in two alternating register sets.
-// The vector work of step s + 1 is interleaved with the products of step s.
+//   * the Omega fragments of step s + 1 and the points of step s + 2 are
+//     requested at the start of step s, in two alternating register sets.
 
 #ifndef LR_B16_WAVES
 #define LR_B16_WAVES 8
 #endif
 constexpr int kB16Waves = LR_B16_WAVES;
+
+__global__ void omega_frag_kernel(const uint16_t* __restrict__ omt, int64_t ld, int64_t n, int d, int64_t nst,
+                                  int64_t total, uint4* __restrict__ frag) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;  // (c16 * nst + s) * 64 + lane
+  if (q >= total) return;
+  const int lane = (int)(q & 63);
+  const int64_t fs = q >> 6;
+  const int64_t c16 = fs / nst;
+  const int64_t step = fs - c16 * nst;
+  const int64_t col = c16 * 16 + (lane & 15);
+  const int64_t j0 = step * kDenseStep + 8 * (lane >> 4);
+  uint4 v = {0u, 0u, 0u, 0u};
+  if (col < d && j0 < n) {
+    const uint16_t* src = omt + col * ld + j0;
+    if (j0 + 8 <= n) {
+      v = *reinterpret_cast<const uint4*>(src);  // j0 and ld are multiples of 8
+    } else {
+      uint16_t t[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) t[e] = (j0 + e < n) ? src[e] : (uint16_t)0;
+      __builtin_memcpy(&v, t, 16);
+    }
+  }
+  frag[q] = v;
+}
 
 template <int E>
 __device__ __forceinline__ float row_bcast(float v) {
@@ -360,9 +387,10 @@ __device__ __forceinline__ float row_bcast(float v) {
 
 template <int NW, int KERNEL, int PD, int ND, int WC, bool DERIV>
 __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __restrict__ pts,
-                                                                     const uint16_t* __restrict__ omt, int64_t ld,
-                                                                     int64_t n, int d, float scale_out, float nu,
-                                                                     float* __restrict__ Y, int nrb, int ncb) {
+                                                                 const uint4* __restrict__ frag, int64_t nst,
+                                                                 const uint16_t* __restrict__ omt, int64_t ld,
+                                                                 int64_t n, int d, float scale_out, float nu,
+                                                                 float* __restrict__ Y, int nrb, int ncb) {
   using K = KernelT<float, KERNEL>;
   using Frag = OmegaFrag<LR_PREC_BF16>;
   constexpr int BN = NW * 16 * WC;
@@ -379,8 +407,6 @@ __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __
   const int gg = wave_uniform(w >> 1);   // generation: j = GPT gg .. GPT gg + GPT - 1 of the step
   const int fl = lane & 15;
   const int fg = lane >> 4;
-  const int64_t nsteps = (n + kDenseStep - 1) / kDenseStep;
-  const int64_t nfull = n / kDenseStep;
   const int nblk = nrb * ncb;
 
   for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
@@ -405,8 +431,8 @@ __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[f][c][i] = 0.0f;
 
-    // x_j of j = 32 step + GPT gg + (fl mod GPT) (inside the zero-padded
-    // point array)
+    // x_j of j = 32 step + GPT gg + (fl mod GPT); the point array has zero
+    // rows past n, and kernel values there meet zero Omega rows
     using Pts = float[ND];
     auto load_pts = [&](int64_t step, Pts& p) {
       const int64_t j = step * kDenseStep + GPT * gg + (fl & (GPT - 1));
@@ -414,9 +440,7 @@ __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __
       for (int t = 0; t < ND; ++t) p[t] = pts[j * PD + t];
     };
     __bf16 gen[GPT];
-    auto generate = [&](int64_t step, const Pts& p, auto full_tag) {
-      constexpr bool FULL = decltype(full_tag)::value;
-      const int64_t j0 = step * kDenseStep + GPT * gg;
+    auto generate = [&](const Pts& p) {
       static_for<0, GPT>([&](auto ee) {
         constexpr int e = decltype(ee)::value;
         float r2 = 0.0f;
@@ -425,9 +449,7 @@ __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __
           const float df = row_bcast<e>(p[t]) - xi[t];
           r2 = __builtin_fmaf(df, df, r2);
         }
-        float val = DERIV ? K::deriv(r2) : K::value(r2);
-        if (!FULL && j0 + e >= n) val = 0.0f;
-        gen[e] = (__bf16)val;
+        gen[e] = (__bf16)(DERIV ? K::deriv(r2) : K::value(r2));
       });
     };
     auto store_gen = [&](int buf) {
@@ -438,53 +460,28 @@ __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __
         for (int e = 0; e < 8; ++e) dst[e] = gen[8 * u + e];
       }
     };
-    // Omega columns of this wave: wave-uniform base (column colw) plus 32-bit
-    // lane offsets; columns >= d read column 0 and feed only accumulator
-    // columns that are never stored.
-    const uint16_t* obase = omt + (int64_t)(colw < d ? colw : 0) * ld;
-    uint32_t coff[WC];
-    bool cok[WC];
+    // this wave's fragments: wave-uniform base plus 32-bit lane offsets
+    const uint4* fbase = frag + (int64_t)(colw / 16) * nst * 64;
+    uint32_t foff[WC];
 #pragma unroll
-    for (int c = 0; c < WC; ++c) {
-      const int col = colw + 16 * c + fl;
-      cok[c] = col < d;
-      coff[c] = cok[c] ? (uint32_t)((int64_t)(16 * c + fl) * ld) : 0u;
-    }
-    // 8 consecutive j of a column in one 16-byte load (jb and ld are multiples
-    // of 8, so a load starting below ld stays inside the column); in the
-    // ragged tail the entries j >= n are cleared in registers.
-    auto load_b = [&](int64_t s, Frag (&dst)[WC], auto full_tag) {
-      constexpr bool FULL = decltype(full_tag)::value;
-      const int64_t jb = s * kDenseStep + 8 * fg;
-      uint32_t keep[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
-      if (!FULL) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          keep[q] = (jb + 2 * q < n ? 0x0000FFFFu : 0u) | (jb + 2 * q + 1 < n ? 0xFFFF0000u : 0u);
-      }
+    for (int c = 0; c < WC; ++c) foff[c] = (uint32_t)((int64_t)c * nst * 64 + lane);
+    auto load_b = [&](int64_t s, Frag (&dst)[WC]) {
+      const uint4* p = fbase + s * 64;
 #pragma unroll
       for (int c = 0; c < WC; ++c) {
-        uint4 raw = {0u, 0u, 0u, 0u};
-        if (FULL || jb < ld) raw = *reinterpret_cast<const uint4*>(obase + coff[c] + jb);
-        if (!FULL) {
-          raw.x &= keep[0];
-          raw.y &= keep[1];
-          raw.z &= keep[2];
-          raw.w &= keep[3];
-        }
+        const uint4 raw = p[foff[c]];
         __builtin_memcpy(&dst[c].v[0], &raw, 16);
       }
     };
-    // Step s: b holds Omega of step s, bl receives Omega of step s + 1
-    // (requested first thing, so nearly a whole step hides its latency), pg
-    // holds the points of step s + 1, pl receives those of step s + 2. FULL:
-    // step s + 1 lies inside [0, n).
-    auto step_body = [&](int64_t s, Frag (&b)[WC], Frag (&bl)[WC], const Pts& pg, Pts& pl, auto full_tag) {
-      constexpr bool FULL = decltype(full_tag)::value;
+    // Step s: b holds Omega of step s, bl receives Omega of step s + 1, pg
+    // holds the points of step s + 1, pl receives those of step s + 2.
+    auto step_body = [&](int64_t s, Frag (&b)[WC], Frag (&bl)[WC], const Pts& pg, Pts& pl) {
       const int cur = (int)(s & 1);
-      const bool has_next = FULL || s + 1 < nsteps;
-      if (has_next) load_b(s + 1, bl, full_tag);
-      if (FULL || s + 2 < nsteps) load_pts(s + 2, pl);
+      const bool has_next = s + 1 < nst;
+      if (has_next) {
+        load_b(s + 1, bl);
+        load_pts(s + 2, pl);
+      }
       Frag a[8];
 #pragma unroll
       for (int f = 0; f < 8; ++f) {
@@ -492,19 +489,11 @@ __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __
 #pragma unroll
         for (int e = 0; e < 8; ++e) a[f].v[e] = src[e];
       }
-      if (has_next) generate(s + 1, pg, full_tag);
+      if (has_next) generate(pg);
 #pragma unroll
       for (int f = 0; f < 8; ++f)
 #pragma unroll
         for (int c = 0; c < WC; ++c) mfma_step<LR_PREC_BF16>(acc[f][c], a[f], b[c]);
-      if constexpr (FULL) {
-        __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);  // the 8 LDS operand reads first
-#pragma unroll
-        for (int i = 0; i < 8 * WC; ++i) {
-          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-          __builtin_amdgcn_sched_group_barrier(0x002, kValuPerMfma, 0);
-        }
-      }
       if (has_next) store_gen(cur ^ 1);
       __syncthreads();
     };
@@ -512,22 +501,19 @@ __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __
     Frag b0[WC], b1[WC];
     Pts p0, p1;
     load_pts(0, p0);
-    generate(0, p0, std::false_type{});
+    generate(p0);
     store_gen(0);
-    load_b(0, b0, std::false_type{});
+    load_b(0, b0);
     load_pts(1, p1);
     __syncthreads();
 
     // pairs of steps with the register sets alternating roles
     int64_t s = 0;
-    for (; s + 2 < nfull; s += 2) {
-      step_body(s, b0, b1, p1, p0, std::true_type{});
-      step_body(s + 1, b1, b0, p0, p1, std::true_type{});
+    for (; s + 1 < nst; s += 2) {
+      step_body(s, b0, b1, p1, p0);
+      step_body(s + 1, b1, b0, p0, p1);
     }
-    for (; s < nsteps; s += 2) {
-      step_body(s, b0, b1, p1, p0, std::false_type{});
-      if (s + 1 < nsteps) step_body(s + 1, b1, b0, p0, p1, std::false_type{});
-    }
+    if (s < nst) step_body(s, b0, b1, p1, p0);
 
 #pragma unroll
     for (int f = 0; f < 8; ++f) {
@@ -538,14 +524,14 @@ __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __
           float* yr = Y + row * d + colw + fl;
 #pragma unroll
           for (int c = 0; c < WC; ++c)
-            if (cok[c]) yr[16 * c] = scale_out * acc[f][c][i];
+            if (colw + 16 * c + fl < d) yr[16 * c] = scale_out * acc[f][c][i];
         }
       }
     }
     if (!DERIV && nu != 0.0f) {  // + nu Omega (Y written by this thread above)
       for (int c = 0; c < WC; ++c) {
-        if (!cok[c]) continue;
         const int col = colw + 16 * c + fl;
+        if (col >= d) continue;
         for (int f = 0; f < 8; ++f)
           for (int i = 0; i < 4; ++i) {
             const int64_t row = row0 + 16 * f + acc_row<f32x4_t>(fg, i);
@@ -556,31 +542,53 @@ __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __
   }
 }
 
+// Columns of the fragment copy: d rounded up to the widest column block.
+int64_t omega_frag_cols(int d) {
+  const int bn = kB16Waves * 16 * 4;
+  return d <= kB16Waves * 16 ? kB16Waves * 16 : (d <= 2 * kB16Waves * 16 ? 2 * kB16Waves * 16 : (d + bn - 1) / bn * bn);
+}
+
+size_t omega_frag_bytes(int64_t n, int d) {
+  const int64_t nst = (n + kDenseStep - 1) / kDenseStep;
+  return (size_t)(omega_frag_cols(d) / 16) * nst * 64 * 16;
+}
+
 template <int KERNEL, int PD, int ND, int WC, bool DERIV>
-static hipError_t launch_bf16_impl(hipStream_t st, const void* pts, const void* omt, int64_t ld, int64_t n, int d,
-                                   double scale_out, double nu, void* Y, int num_cu) {
+static hipError_t launch_bf16_impl(hipStream_t st, const void* pts, const uint4* frag, const void* omt, int64_t ld,
+                                   int64_t n, int d, double scale_out, double nu, void* Y, int num_cu) {
   constexpr int NW = kB16Waves;
   constexpr int BN = NW * 16 * WC;
   const int nrb = (int)((n + kDenseRows - 1) / kDenseRows);
   const int ncb = (d + BN - 1) / BN;
+  const int64_t nst = (n + kDenseStep - 1) / kDenseStep;
   int64_t blocks = (int64_t)nrb * ncb;
   if (blocks > num_cu) blocks = num_cu;
   hipLaunchKernelGGL((sketch_bf16_kernel<NW, KERNEL, PD, ND, WC, DERIV>), dim3((unsigned)blocks), dim3(NW * 64), 0,
-                     st, (const float*)pts, (const uint16_t*)omt, ld, n, d, (float)scale_out, (float)nu, (float*)Y,
-                     nrb, ncb);
+                     st, (const float*)pts, frag, nst, (const uint16_t*)omt, ld, n, d, (float)scale_out, (float)nu,
+                     (float*)Y, nrb, ncb);
   return hipGetLastError();
 }
 
 template <int KERNEL, int PD, int ND, bool DERIV>
-static hipError_t launch_bf16_wc(hipStream_t st, const void* pts, const void* omt, int64_t ld, int64_t n, int d,
-                                 double so, double nu, void* Y, int num_cu) {
+static hipError_t launch_bf16_wc(hipStream_t st, const void* pts, const uint4* frag, const void* omt, int64_t ld,
+                                 int64_t n, int d, double so, double nu, void* Y, int num_cu) {
   constexpr int cols_per_wc = kB16Waves * 16;
-  if (d <= cols_per_wc) return launch_bf16_impl<KERNEL, PD, ND, 1, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
+  if (d <= cols_per_wc)
+    return launch_bf16_impl<KERNEL, PD, ND, 1, DERIV>(st, pts, frag, omt, ld, n, d, so, nu, Y, num_cu);
   if (d <= 2 * cols_per_wc)
-    return launch_bf16_impl<KERNEL, PD, ND, 2, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
-  // WC = 8 (512 accumulator registers per wave with 4 waves) does not fit the
-  // register file with the operands; larger d takes several column blocks
-  return launch_bf16_impl<KERNEL, PD, ND, 4, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
+    return launch_bf16_impl<KERNEL, PD, ND, 2, DERIV>(st, pts, frag, omt, ld, n, d, so, nu, Y, num_cu);
+  // wider column blocks do not fit the register file with the operands;
+  // larger d takes several column blocks
+  return launch_bf16_impl<KERNEL, PD, ND, 4, DERIV>(st, pts, frag, omt, ld, n, d, so, nu, Y, num_cu);
+}
+
+hipError_t launch_omega_frag(hipStream_t st, const void* omt, int64_t ld, int64_t n, int d, void* frag) {
+  const int64_t nst = (n + kDenseStep - 1) / kDenseStep;
+  const int64_t total = omega_frag_cols(d) / 16 * nst * 64;
+  const int threads = 256;
+  hipLaunchKernelGGL(omega_frag_kernel, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0, st,
+                     (const uint16_t*)omt, ld, n, d, nst, total, (uint4*)frag);
+  return hipGetLastError();
 }
 
 template <int PREC, int KERNEL, int PD, int ND, int WN, bool DERIV>
@@ -614,48 +622,56 @@ static hipError_t launch_dense_wn(hipStream_t st, const void* pts, const void* o
 // Coordinates used: D itself for D <= 3 (stride 4), else every slot but the sign.
 template <int PREC, int KERNEL, bool DERIV>
 static hipError_t launch_dense_dim(hipStream_t st, int D, const void* pts, const void* omt, int64_t ld, int64_t n,
-                                   int d, double so, double nu, void* Y, int num_cu) {
-  // bf16 with a point stride of 4 and 32-bit Omega lane offsets: one wave per SIMD
+                                   int d, double so, double nu, void* Y, const void* frag, int num_cu) {
   if constexpr (PREC == LR_PREC_BF16) {
-    if (D <= 3 && (int64_t)128 * ld < ((int64_t)1 << 32)) {
+    // D <= 3 (point stride 4): the matrix-core kernel on the fragment copy
+    if (D <= 3) {
+      if (frag == nullptr) return hipErrorInvalidValue;
+      const uint4* f = static_cast<const uint4*>(frag);
       switch (D) {
-        case 1: return launch_bf16_wc<KERNEL, 4, 1, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
-        case 2: return launch_bf16_wc<KERNEL, 4, 2, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
-        default: return launch_bf16_wc<KERNEL, 4, 3, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
+        case 1: return launch_bf16_wc<KERNEL, 4, 1, DERIV>(st, pts, f, omt, ld, n, d, so, nu, Y, num_cu);
+        case 2: return launch_bf16_wc<KERNEL, 4, 2, DERIV>(st, pts, f, omt, ld, n, d, so, nu, Y, num_cu);
+        default: return launch_bf16_wc<KERNEL, 4, 3, DERIV>(st, pts, f, omt, ld, n, d, so, nu, Y, num_cu);
       }
     }
-  }
-  switch (D) {
-    case 1: return launch_dense_wn<PREC, KERNEL, 4, 1, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
-    case 2: return launch_dense_wn<PREC, KERNEL, 4, 2, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
-    case 3: return launch_dense_wn<PREC, KERNEL, 4, 3, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
-    default:
-      if (D <= 7) return launch_dense_wn<PREC, KERNEL, 8, 7, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
-      return launch_dense_wn<PREC, KERNEL, 16, 15, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
+    if (D <= 7) return launch_dense_wn<PREC, KERNEL, 8, 7, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
+    return launch_dense_wn<PREC, KERNEL, 16, 15, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
+  } else {
+    (void)frag;
+    // Coordinates used: D itself for D <= 3 (stride 4), else every slot but the sign.
+    switch (D) {
+      case 1: return launch_dense_wn<PREC, KERNEL, 4, 1, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
+      case 2: return launch_dense_wn<PREC, KERNEL, 4, 2, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
+      case 3: return launch_dense_wn<PREC, KERNEL, 4, 3, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
+      default:
+        if (D <= 7) return launch_dense_wn<PREC, KERNEL, 8, 7, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
+        return launch_dense_wn<PREC, KERNEL, 16, 15, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
+    }
   }
 }
 
 template <int PREC, bool DERIV>
 static hipError_t launch_dense_prec(hipStream_t st, int kernel, int D, const void* pts, const void* omt,
-                                   int64_t ld, int64_t n, int d, double so, double nu, void* Y, int num_cu) {
+                                    int64_t ld, int64_t n, int d, double so, double nu, void* Y, const void* frag,
+                                    int num_cu) {
   if (kernel == LR_KERNEL_SE)
-    return launch_dense_dim<PREC, LR_KERNEL_SE, DERIV>(st, D, pts, omt, ld, n, d, so, nu, Y, num_cu);
-  return launch_dense_dim<PREC, LR_KERNEL_MATERN32, DERIV>(st, D, pts, omt, ld, n, d, so, nu, Y, num_cu);
+    return launch_dense_dim<PREC, LR_KERNEL_SE, DERIV>(st, D, pts, omt, ld, n, d, so, nu, Y, frag, num_cu);
+  return launch_dense_dim<PREC, LR_KERNEL_MATERN32, DERIV>(st, D, pts, omt, ld, n, d, so, nu, Y, frag, num_cu);
 }
 
 hipError_t launch_sketch_dense(hipStream_t st, int prec, int kernel, int D, const void* pts, const void* omt,
-                               int64_t ld, int64_t n, int d, double scale_out, double nu, void* Y, bool deriv,
-                               int num_cu) {
+                               int64_t ld, int64_t n, int d, double so, double nu, void* Y, bool deriv,
+                               const void* frag, int num_cu) {
   if (prec == LR_PREC_BF16) {
-    return deriv ? launch_dense_prec<LR_PREC_BF16, true>(st, kernel, D, pts, omt, ld, n, d, scale_out, nu, Y, num_cu)
-                 : launch_dense_prec<LR_PREC_BF16, false>(st, kernel, D, pts, omt, ld, n, d, scale_out, nu, Y, num_cu);
+    return deriv ? launch_dense_prec<LR_PREC_BF16, true>(st, kernel, D, pts, omt, ld, n, d, so, nu, Y, frag, num_cu)
+                 : launch_dense_prec<LR_PREC_BF16, false>(st, kernel, D, pts, omt, ld, n, d, so, nu, Y, frag, num_cu);
   }
   if (prec == LR_PREC_F32) {
-    return deriv ? launch_dense_prec<LR_PREC_F32, true>(st, kernel, D, pts, omt, ld, n, d, scale_out, nu, Y, num_cu)
-                 : launch_dense_prec<LR_PREC_F32, false>(st, kernel, D, pts, omt, ld, n, d, scale_out, nu, Y, num_cu);
+    return deriv ? launch_dense_prec<LR_PREC_F32, true>(st, kernel, D, pts, omt, ld, n, d, so, nu, Y, frag, num_cu)
+                 : launch_dense_prec<LR_PREC_F32, false>(st, kernel, D, pts, omt, ld, n, d, so, nu, Y, frag, num_cu);
   }
-  return deriv ? launch_dense_prec<LR_PREC_F64, true>(st, kernel, D, pts, omt, ld, n, d, scale_out, nu, Y, num_cu)
-               : launch_dense_prec<LR_PREC_F64, false>(st, kernel, D, pts, omt, ld, n, d, scale_out, nu, Y, num_cu);
+  return deriv ? launch_dense_prec<LR_PREC_F64, true>(st, kernel, D, pts, omt, ld, n, d, so, nu, Y, frag, num_cu)
+               : launch_dense_prec<LR_PREC_F64, false>(st, kernel, D, pts, omt, ld, n, d, so, nu, Y, frag, num_cu);
 }
 
 }  // namespace lr
