@@ -109,7 +109,7 @@ lr_status lr_check_srht_cols(const int32_t *cols_host, int32_t d, int64_t n);
  *   Yprime  device real n x d output of (dK_f / dlog ell) Omega, or NULL. With
  *           SRHT and F32 both outputs come from one fused pass.
  * Unsupported: BF16 with SRHT.
- * Workspace: the prescaled points ((n + 64) rows) and, for BF16 with D <= 3, a
+ * Workspace: the prescaled points ((n + 128) rows) and, for BF16 with D <= 3, a
  * copy of the Gaussian Omega in matrix-core operand order (about 2 n d bytes). */
 size_t lr_sketch_workspace_bytes(int64_t n, int32_t D, int32_t d, int32_t prec);
 lr_status lr_sketch(void *stream, int64_t n, int32_t D, const float *X, const lr_hyper *hyp,

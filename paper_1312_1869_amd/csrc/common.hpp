@@ -15,7 +15,7 @@ typedef double f64x4_t __attribute__((ext_vector_type(4)));
 namespace lr {
 
 // zero rows appended to the prescaled point array
-constexpr int kPointPad = 64;
+constexpr int kPointPad = 128;
 
 constexpr double kLog2e = 1.4426950408889634074;
 constexpr double kLn2 = 0.69314718055994530942;

@@ -346,8 +346,9 @@ __global__ __launch_bounds__(512, 1) void sketch_dense_kernel(
 //   * the entries are rounded to bf16 and written to a double-buffered LDS
 //     tile in operand order; each wave reads the 8 row fragments of the tile
 //     and multiplies them with its WC Omega fragments (8 x WC products);
-//   * the Omega fragments of step s + 1 and the points of step s + 2 are
-//     requested at the start of step s, in two alternating register sets.
+//   * the Omega fragments of step s + 1 (two alternating register sets) and
+//     the points of step s + 3 (three rotating sets) are requested at the
+//     start of step s.
 
 #ifndef LR_B16_WAVES
 #define LR_B16_WAVES 8
@@ -431,8 +432,9 @@ __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[f][c][i] = 0.0f;
 
-    // x_j of j = 32 step + GPT gg + (fl mod GPT); the point array has zero
-    // rows past n, and kernel values there meet zero Omega rows
+    // x_j of j = 32 step + GPT gg + (fl mod GPT); the point array has
+    // kPointPad zero rows past n (steps up to nst + 2 are read), and kernel
+    // values there meet zero Omega rows
     using Pts = float[ND];
     auto load_pts = [&](int64_t step, Pts& p) {
       const int64_t j = step * kDenseStep + GPT * gg + (fl & (GPT - 1));
@@ -474,14 +476,14 @@ __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __
       }
     };
     // Step s: b holds Omega of step s, bl receives Omega of step s + 1, pg
-    // holds the points of step s + 1, pl receives those of step s + 2.
+    // holds the points of step s + 1, pl receives those of step s + 3. The
+    // loads, the evaluation and the tile store are unconditional (the last
+    // steps read the zero padding past the data and their tiles are never
+    // used), so no branch hides from the compiler how many loads are in flight.
     auto step_body = [&](int64_t s, Frag (&b)[WC], Frag (&bl)[WC], const Pts& pg, Pts& pl) {
       const int cur = (int)(s & 1);
-      const bool has_next = s + 1 < nst;
-      if (has_next) {
-        load_b(s + 1, bl);
-        load_pts(s + 2, pl);
-      }
+      load_b(s + 1, bl);
+      load_pts(s + 3, pl);
       Frag a[8];
 #pragma unroll
       for (int f = 0; f < 8; ++f) {
@@ -489,31 +491,41 @@ __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __
 #pragma unroll
         for (int e = 0; e < 8; ++e) a[f].v[e] = src[e];
       }
-      if (has_next) generate(pg);
+      generate(pg);
 #pragma unroll
       for (int f = 0; f < 8; ++f)
 #pragma unroll
         for (int c = 0; c < WC; ++c) mfma_step<LR_PREC_BF16>(acc[f][c], a[f], b[c]);
-      if (has_next) store_gen(cur ^ 1);
+      store_gen(cur ^ 1);
       __syncthreads();
+      // keep each step's instructions inside the step, so loads issued at its
+      // start are not sunk towards their uses one or two steps later
+      __builtin_amdgcn_sched_barrier(0);
     };
 
-    Frag b0[WC], b1[WC];
-    Pts p0, p1;
-    load_pts(0, p0);
-    generate(p0);
+    // Omega in 2 alternating register sets (one step ahead), points in 3
+    // rotating sets (two steps ahead): six steps per loop trip.
+    Frag bs[2][WC];
+    Pts ps[3];
+    load_pts(0, ps[0]);
+    generate(ps[0]);
     store_gen(0);
-    load_b(0, b0);
-    load_pts(1, p1);
+    load_b(0, bs[0]);
+    load_pts(1, ps[1]);
+    load_pts(2, ps[2]);
     __syncthreads();
 
-    // pairs of steps with the register sets alternating roles
     int64_t s = 0;
-    for (; s + 1 < nst; s += 2) {
-      step_body(s, b0, b1, p1, p0);
-      step_body(s + 1, b1, b0, p0, p1);
+    for (; s + 6 <= nst; s += 6) {
+      static_for<0, 6>([&](auto kk) {
+        constexpr int k = decltype(kk)::value;
+        step_body(s + k, bs[k % 2], bs[(k + 1) % 2], ps[(k + 1) % 3], ps[k % 3]);
+      });
     }
-    if (s < nst) step_body(s, b0, b1, p1, p0);
+    static_for<0, 5>([&](auto kk) {
+      constexpr int k = decltype(kk)::value;
+      if (s + k < nst) step_body(s + k, bs[k % 2], bs[(k + 1) % 2], ps[(k + 1) % 3], ps[k % 3]);
+    });
 
 #pragma unroll
     for (int f = 0; f < 8; ++f) {
@@ -548,9 +560,10 @@ int64_t omega_frag_cols(int d) {
   return d <= kB16Waves * 16 ? kB16Waves * 16 : (d <= 2 * kB16Waves * 16 ? 2 * kB16Waves * 16 : (d + bn - 1) / bn * bn);
 }
 
+// plus one zero step of padding, read by the last step's (unused) prefetch
 size_t omega_frag_bytes(int64_t n, int d) {
   const int64_t nst = (n + kDenseStep - 1) / kDenseStep;
-  return (size_t)(omega_frag_cols(d) / 16) * nst * 64 * 16;
+  return ((size_t)(omega_frag_cols(d) / 16) * nst + 1) * 64 * 16;
 }
 
 template <int KERNEL, int PD, int ND, int WC, bool DERIV>
@@ -584,7 +597,7 @@ static hipError_t launch_bf16_wc(hipStream_t st, const void* pts, const uint4* f
 
 hipError_t launch_omega_frag(hipStream_t st, const void* omt, int64_t ld, int64_t n, int d, void* frag) {
   const int64_t nst = (n + kDenseStep - 1) / kDenseStep;
-  const int64_t total = omega_frag_cols(d) / 16 * nst * 64;
+  const int64_t total = (omega_frag_cols(d) / 16 * nst + 1) * 64;  // the last step is the zero pad
   const int threads = 256;
   hipLaunchKernelGGL(omega_frag_kernel, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0, st,
                      (const uint16_t*)omt, ld, n, d, nst, total, (uint4*)frag);
