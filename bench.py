@@ -206,7 +206,7 @@ def main() -> int:
 
     src = source_hash("paper_1312_1869_amd/csrc/sketch_dense.hip", "paper_1312_1869_amd/csrc/common.hpp")
     if w.omega == "gauss":
-        kernel_key = {"bf16": "sketch_dense_kernel<2", "f32": "sketch_dense_kernel<1",
+        kernel_key = {"bf16": "sketch_bf16_kernel", "f32": "sketch_dense_kernel<1",
                       "f64": "sketch_dense_kernel<0"}[prec]
         peak, unit, bound = (PEAKS["bf16_tflops"] if prec == "bf16" else
                              PEAKS["fp32_tflops"] if prec == "f32" else PEAKS["fp64_tflops"]), "TFLOP/s", "mfma"

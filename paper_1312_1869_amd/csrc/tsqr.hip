@@ -7,12 +7,13 @@
 //   * Q formation (Eq. 4): Q = blockdiag(leaf Q) (tree Q) [I; 0] is built top
 //     down: every node maps its d x d block M to Q_node [M; 0], whose halves are
 //     the children's blocks, and every leaf writes its rows Q_leaf [M_leaf; 0].
-// A panel of NB columns is factored by one 1024-thread workgroup per matrix
+// A panel of NB columns is factored by one 512-thread workgroup per matrix
 // (rows in registers, one block reduction per reflector), producing LAPACK
 // style reflectors (beta = -sign(alpha) |x|, tau = 0 when the part below the
 // diagonal is zero) and the compact-WY factor T with H_1 ... H_NB = I - V T V^T.
-// The trailing columns and Q formation are rank-NB updates B -= V (T' (V^T B))
-// spread over (column block x matrix) workgroups.
+// Inner panels are applied only inside an outer panel of 64 columns; the
+// trailing columns and the Q formation take one rank-64 update
+// B -= V (T' (V^T B)) per outer panel on the matrix cores.
 #include <vector>
 
 #include "common.hpp"
@@ -383,6 +384,269 @@ __global__ __launch_bounds__(kUpdThreads) void panel_apply_kernel(const T* Vmat,
   }
 }
 
+// ---------------------------------------------------------------- outer panels
+//
+// Two-level blocking: inner panels of NB columns (above) are factored and
+// applied only inside an outer panel of kOuter = 64 columns; the outer panel's
+// reflectors are then combined into one compact-WY factor T_big (64 x 64,
+// block_t_kernel, from the inner T's and the Gram matrix V^T V) and applied to
+// the trailing columns, or to the block being turned into Q, by
+// block_apply_kernel: W = V^T B, W' = T' W, B -= V W', with both products on
+// the matrix cores (16x16x4 in float or double). One 256-thread workgroup owns
+// 64 columns of B of one matrix; its 4 waves split the rows.
+constexpr int kOuter = 64;
+constexpr int kBlkThreads = 256;
+
+template <typename T>
+struct BlkMfma;
+template <>
+struct BlkMfma<float> {
+  using Acc = f32x4_t;
+  __device__ __forceinline__ static Acc step(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct BlkMfma<double> {
+  using Acc = f64x4_t;
+  __device__ __forceinline__ static Acc step(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+// x[0..3] = src[0..3] for the columns c0 .. c0+3 that are < cend (others 0).
+template <typename T>
+__device__ __forceinline__ void load4(const T* src, int c0, int cend, bool vec, T (&x)[4]) {
+  if (vec && c0 + 4 <= cend) {
+    if constexpr (sizeof(T) == 4) {
+      const float4 v = *reinterpret_cast<const float4*>(src);
+      x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+    } else {
+      const double2 u = *reinterpret_cast<const double2*>(src);
+      const double2 v = *reinterpret_cast<const double2*>(src + 2);
+      x[0] = u.x; x[1] = u.y; x[2] = v.x; x[3] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) x[t] = (c0 + t < cend) ? src[t] : (T)0;
+  }
+}
+
+// MODE 0: B <- (I - V T^T V^T) B   (factorisation, Q^T B)
+// MODE 1: B <- (I - V T V^T) B     (Q formation, Q B)
+// MODE 2: gout = V^T V             (Gram matrix of the outer panel)
+// V = columns [P0, P0 + W) of Vmat with unit diagonal and zeros above, over the
+// rows of the outer panel's row map; B columns [col_begin, col_end).
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlkThreads) void block_apply_kernel(const T* Vmat, int64_t vstride, T* Bmat,
+                                                                  int64_t bstride, int m_full, int m_last,
+                                                                  int nbatch, int ld, int P0, int W, int tree_d,
+                                                                  int col_begin, int col_end,
+                                                                  const T* __restrict__ tbig, T* __restrict__ gout) {
+  using M = BlkMfma<T>;
+  using Acc = typename M::Acc;
+  __shared__ T Ws[kOuter][kOuter + 1];
+  __shared__ T Ts[kOuter][kOuter + 1];
+
+  const int b = blockIdx.y;
+  const int m = (b == nbatch - 1) ? m_last : m_full;
+  const T* V = Vmat + (int64_t)b * vstride;
+  T* B = Bmat + (int64_t)b * bstride;
+  const RowMap rm = make_rowmap<kOuter>(m, P0, tree_d);
+  const int nact = rm.nact;
+  const int t = threadIdx.x;
+  const int w = t >> 6;
+  const int lane = t & 63;
+  const int l15 = lane & 15;
+  const int lg = lane >> 4;
+  const int cb0 = (MODE == 2) ? P0 : col_begin + blockIdx.x * kOuter;
+  const int cend = (MODE == 2) ? P0 + W : col_end;
+  const bool vec_ld = ((int64_t)ld * sizeof(T)) % 16 == 0;
+  const bool vec_v = vec_ld && (reinterpret_cast<uintptr_t>(V) % 16 == 0) && (P0 % 4 == 0);
+  const bool vec_b = vec_ld && (reinterpret_cast<uintptr_t>(B) % 16 == 0) && (cb0 % 4 == 0);
+
+  // 4 consecutive panel columns 4q .. 4q+3 of compact row ci, masked to the
+  // unit lower trapezoid (zero for ci >= nact)
+  auto vrow4 = [&](int ci, int q, T (&x)[4]) {
+    if (ci >= nact) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) x[e] = 0;
+      return;
+    }
+    load4<T>(V + (int64_t)rm.row(ci) * ld + P0 + 4 * q, P0 + 4 * q, P0 + W, vec_v, x);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = 4 * q + e;
+      x[e] = (ci > i) ? x[e] : (ci == i ? (T)1 : (T)0);
+    }
+  };
+
+  // ---- pass 1: W = V^T B (tile (ti, tj) entry (r, c) is W[4r + ti][4c + tj])
+  Acc acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[a][c][e] = 0;
+  for (int r0 = 4 * w; r0 < nact; r0 += 16) {
+    const int ci = r0 + lg;
+    T va[4], vb[4];
+    vrow4(ci, l15, va);
+    if (MODE == 2) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) vb[e] = va[e];
+    } else if (ci < nact) {
+      load4<T>(B + (int64_t)rm.row(ci) * ld + cb0 + 4 * l15, cb0 + 4 * l15, cend, vec_b, vb);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) vb[e] = 0;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[a][c] = M::step(va[a], vb[c], acc[a][c]);
+  }
+  // combine the 4 waves' partial sums in LDS, one wave after the other
+  for (int ww = 0; ww < 4; ++ww) {
+    if (w == ww) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int i = 4 * acc_row<Acc>(lg, e) + a;
+            const int j = 4 * l15 + c;
+            Ws[i][j] = (ww == 0) ? acc[a][c][e] : Ws[i][j] + acc[a][c][e];
+          }
+    }
+    __syncthreads();
+  }
+  if (MODE == 2) {
+    T* g = gout + (int64_t)b * kOuter * kOuter;
+    for (int e = t; e < kOuter * kOuter; e += kBlkThreads) g[e] = Ws[e / kOuter][e % kOuter];
+    return;
+  }
+
+  // ---- W' = T' W (T' = T^T for MODE 0, T for MODE 1); T is upper triangular
+  const T* tb = tbig + (int64_t)b * kOuter * kOuter;
+  for (int e = t; e < kOuter * kOuter; e += kBlkThreads) Ts[e / kOuter][e % kOuter] = tb[e];
+  __syncthreads();
+  T wp[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = t + q * kBlkThreads;
+    const int i = e / kOuter, j = e % kOuter;
+    T sum = 0;
+    if (MODE == 0) {
+      for (int k = 0; k <= i; ++k) sum += Ts[k][i] * Ws[k][j];
+    } else {
+      for (int k = i; k < kOuter; ++k) sum += Ts[i][k] * Ws[k][j];
+    }
+    wp[q] = sum;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = t + q * kBlkThreads;
+    Ws[e / kOuter][e % kOuter] = wp[q];
+  }
+  __syncthreads();
+
+  // ---- pass 2: B -= V W'. Step (q, u) uses panel columns k = 16q + 4lg + u;
+  // output tile tc covers B columns cb0 + 16 tc .. + 15.
+  T wb[4][4][4];  // [q][u][tc] = W'[16q + 4lg + u][16 tc + l15]
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int tc = 0; tc < 4; ++tc) wb[q][u][tc] = Ws[16 * q + 4 * lg + u][16 * tc + l15];
+  for (int c0 = 16 * w; c0 < nact; c0 += 64) {
+    T va[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      T x[4];
+      vrow4(c0 + l15, 4 * q + lg, x);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) va[q][u] = x[u];
+    }
+    Acc out[4];
+#pragma unroll
+    for (int tc = 0; tc < 4; ++tc)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) out[tc][e] = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int tc = 0; tc < 4; ++tc) out[tc] = M::step(va[q][u], wb[q][u][tc], out[tc]);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int ci = c0 + acc_row<Acc>(lg, e);
+      if (ci < nact) {
+        T* dst = B + (int64_t)rm.row(ci) * ld + cb0 + l15;
+#pragma unroll
+        for (int tc = 0; tc < 4; ++tc)
+          if (cb0 + 16 * tc + l15 < cend) dst[16 * tc] -= out[tc][e];
+      }
+    }
+  }
+}
+
+// T_big (kOuter x kOuter, upper triangular) of the outer panel [P0, P0 + W)
+// from the inner factors T_k (nb x nb, at tm + (P0/nb + k) nb^2) and the Gram
+// matrix G = V^T V: merging block k into the leading blocks 0..k-1 sets
+//   T_big[0:k nb, k nb : k nb + nb] = -T_big[0:k nb, 0:k nb] G[0:k nb, k-th block] T_k.
+// Entries outside the W x W block are zero.
+template <typename T>
+__global__ __launch_bounds__(kBlkThreads) void block_t_kernel(const T* __restrict__ tm, int64_t t_bstride, int nb,
+                                                              int P0, int W, const T* __restrict__ gram,
+                                                              T* __restrict__ tbig) {
+  __shared__ T Tb[kOuter][kOuter + 1];
+  __shared__ T G[kOuter][kOuter + 1];
+  __shared__ T X[kOuter][kOuter + 1];
+  const int b = blockIdx.x;
+  const int t = threadIdx.x;
+  const T* g = gram + (int64_t)b * kOuter * kOuter;
+  for (int e = t; e < kOuter * kOuter; e += kBlkThreads) {
+    const int i = e / kOuter, j = e % kOuter;
+    G[i][j] = g[e];
+    T v = 0;
+    if (i < W && j < W && i / nb == j / nb && i <= j) {
+      const int k = i / nb;
+      v = tm[(int64_t)b * t_bstride + (int64_t)(P0 / nb + k) * nb * nb + (i - k * nb) * nb + (j - k * nb)];
+    }
+    Tb[i][j] = v;
+  }
+  __syncthreads();
+  const int K = (W + nb - 1) / nb;
+  for (int k = 1; k < K; ++k) {
+    const int r = k * nb;                // rows of the leading part
+    const int nbk = min(nb, W - r);      // width of block k
+    // X = Tb[0:r, 0:r] G[0:r, r:r+nbk]
+    for (int e = t; e < r * nbk; e += kBlkThreads) {
+      const int i = e / nbk, j = e % nbk;
+      T sum = 0;
+      for (int q = i; q < r; ++q) sum += Tb[i][q] * G[q][r + j];
+      X[i][j] = sum;
+    }
+    __syncthreads();
+    // Tb[0:r, r:r+nbk] = -X T_k
+    for (int e = t; e < r * nbk; e += kBlkThreads) {
+      const int i = e / nbk, j = e % nbk;
+      T sum = 0;
+      for (int q = 0; q <= j; ++q) sum += X[i][q] * Tb[r + q][r + j];
+      Tb[i][r + j] = -sum;
+    }
+    __syncthreads();
+  }
+  T* out = tbig + (int64_t)b * kOuter * kOuter;
+  for (int e = t; e < kOuter * kOuter; e += kBlkThreads) out[e] = Tb[e / kOuter][e % kOuter];
+}
+
 // Rdst[b] = upper triangle of the top d x d block of src[b] (as double, zeros below).
 template <typename T>
 __global__ void extract_r_kernel(const T* __restrict__ src, int64_t sstride, int ld, int d,
@@ -510,35 +774,62 @@ static hipError_t launch_apply(hipStream_t st, int nb, const T* V, int64_t vstri
     if (e__ != hipSuccess) return e__;     \
   } while (0)
 
+template <typename T, int MODE>
+static hipError_t launch_block_apply(hipStream_t st, const T* V, int64_t vstride, T* B, int64_t bstride,
+                                     const QrShape& s, int P0, int W, int c0, int c1, const T* tbig, T* gout) {
+  const int ncb = (MODE == 2) ? 1 : (c1 - c0 + kOuter - 1) / kOuter;
+  if (ncb <= 0) return hipSuccess;
+  hipLaunchKernelGGL((block_apply_kernel<T, MODE>), dim3(ncb, s.nbatch), dim3(kBlkThreads), 0, st, V, vstride, B,
+                     bstride, s.m_full, s.m_last, s.nbatch, s.d, P0, W, s.tree_d, c0, c1, tbig, gout);
+  return hipGetLastError();
+}
+
+// Number of outer panels and the T_big / Gram storage they need per matrix.
+static int n_outer(int d) { return (d + kOuter - 1) / kOuter; }
+
 // Batched Householder QR in place: A[b] (m_b x d, ld d) -> R (upper) + V (below).
+// Inner panels are factored and applied inside each outer panel; the outer
+// panel's T_big (kept in tbig for the Q formation) then updates the trailing
+// columns in one pass.
 template <typename T>
-static hipError_t batched_qr(hipStream_t st, T* A, int64_t bstride, const QrShape& s, T* tau, T* tm) {
+static hipError_t batched_qr(hipStream_t st, T* A, int64_t bstride, const QrShape& s, T* tau, T* tm, T* tbig,
+                             T* gram) {
   const int rpt = pick_rpt(s.m_full > s.m_last ? s.m_full : s.m_last);
-  for (int p = 0; p < s.npanels; ++p) {
-    const int p0 = p * s.nb;
-    const int nbw = (s.d - p0) < s.nb ? (s.d - p0) : s.nb;
-    T* tmp = tm + (int64_t)p * s.nb * s.nb;
-    if (s.nb == 16) {
-      LR_TRY((launch_panel_factor_nb<T, 16>(st, rpt, A, bstride, s, p0, nbw, tau, tmp)));
-    } else if (s.nb == 8) {
-      LR_TRY((launch_panel_factor_nb<T, 8>(st, rpt, A, bstride, s, p0, nbw, tau, tmp)));
-    } else {
-      LR_TRY((launch_panel_factor_nb<T, 4>(st, rpt, A, bstride, s, p0, nbw, tau, tmp)));
+  const int64_t t_bstride = (int64_t)s.npanels * s.nb * s.nb;
+  for (int o = 0; o < n_outer(s.d); ++o) {
+    const int P0 = o * kOuter;
+    const int W = (s.d - P0) < kOuter ? (s.d - P0) : kOuter;
+    for (int p0 = P0; p0 < P0 + W; p0 += s.nb) {
+      const int nbw = (s.d - p0) < s.nb ? (s.d - p0) : s.nb;
+      T* tmp = tm + (int64_t)(p0 / s.nb) * s.nb * s.nb;
+      if (s.nb == 16) {
+        LR_TRY((launch_panel_factor_nb<T, 16>(st, rpt, A, bstride, s, p0, nbw, tau, tmp)));
+      } else if (s.nb == 8) {
+        LR_TRY((launch_panel_factor_nb<T, 8>(st, rpt, A, bstride, s, p0, nbw, tau, tmp)));
+      } else {
+        LR_TRY((launch_panel_factor_nb<T, 4>(st, rpt, A, bstride, s, p0, nbw, tau, tmp)));
+      }
+      LR_TRY((launch_apply<T, true>(st, s.nb, A, bstride, A, bstride, s, p0, nbw, p0 + nbw, P0 + W, tmp)));
     }
-    LR_TRY((launch_apply<T, true>(st, s.nb, A, bstride, A, bstride, s, p0, nbw, p0 + nbw, s.d, tmp)));
+    T* tb = tbig + (int64_t)o * s.nbatch * kOuter * kOuter;
+    LR_TRY((launch_block_apply<T, 2>(st, A, bstride, A, bstride, s, P0, W, 0, 0, nullptr, gram)));
+    hipLaunchKernelGGL(block_t_kernel<T>, dim3(s.nbatch), dim3(kBlkThreads), 0, st, tm, t_bstride, s.nb, P0, W, gram,
+                       tb);
+    LR_TRY(hipGetLastError());
+    LR_TRY((launch_block_apply<T, 0>(st, A, bstride, A, bstride, s, P0, W, P0 + W, s.d, tb, nullptr)));
   }
   return hipSuccess;
 }
 
-// B[b] <- Q[b] B[b] with Q[b] from batched_qr (panels applied last to first).
+// B[b] <- Q[b] B[b] with Q[b] from batched_qr (outer panels last to first).
 template <typename T>
 static hipError_t batched_apply_q(hipStream_t st, const T* V, int64_t vstride, T* B, int64_t bstride,
-                                  const QrShape& s, const T* tm) {
-  for (int p = s.npanels - 1; p >= 0; --p) {
-    const int p0 = p * s.nb;
-    const int nbw = (s.d - p0) < s.nb ? (s.d - p0) : s.nb;
-    LR_TRY((launch_apply<T, false>(st, s.nb, V, vstride, B, bstride, s, p0, nbw, 0, s.d,
-                                   tm + (int64_t)p * s.nb * s.nb)));
+                                  const QrShape& s, const T* tbig) {
+  for (int o = n_outer(s.d) - 1; o >= 0; --o) {
+    const int P0 = o * kOuter;
+    const int W = (s.d - P0) < kOuter ? (s.d - P0) : kOuter;
+    LR_TRY((launch_block_apply<T, 1>(st, V, vstride, B, bstride, s, P0, W, 0, s.d,
+                                     tbig + (int64_t)o * s.nbatch * kOuter * kOuter, nullptr)));
   }
   return hipSuccess;
 }
@@ -551,8 +842,8 @@ struct TsqrPlan {
   std::vector<int> count;  // R factors per level (level 0 = leaves)
   std::vector<int> pairs;  // nodes per tree level
   // offsets into the workspace
-  size_t off_work, off_tau, off_t;
-  std::vector<size_t> off_r, off_m, off_node, off_ntau, off_nt;
+  size_t off_work, off_tau, off_t, off_tbig, off_gram;
+  std::vector<size_t> off_r, off_m, off_node, off_ntau, off_nt, off_ntbig, off_ngram;
   size_t total;
 };
 
@@ -572,6 +863,11 @@ static TsqrPlan make_plan(int64_t n, int d, int leaf_rows) {
   off = align256(off + (size_t)p.nleaf * d * sizeof(T));
   p.off_t = off;
   off = align256(off + (size_t)p.nleaf * ls.npanels * ls.nb * ls.nb * sizeof(T));
+  const size_t blk = (size_t)kOuter * kOuter;
+  p.off_tbig = off;
+  off = align256(off + (size_t)n_outer(d) * p.nleaf * blk * sizeof(T));
+  p.off_gram = off;
+  off = align256(off + (size_t)p.nleaf * blk * sizeof(T));
   int c = p.nleaf;
   p.count.push_back(c);
   while (c > 1) {
@@ -594,6 +890,10 @@ static TsqrPlan make_plan(int64_t n, int d, int leaf_rows) {
     off = align256(off + (size_t)p.pairs[l] * d * sizeof(double));
     p.off_nt.push_back(off);
     off = align256(off + (size_t)p.pairs[l] * ns.npanels * ns.nb * ns.nb * sizeof(double));
+    p.off_ntbig.push_back(off);
+    off = align256(off + (size_t)n_outer(d) * p.pairs[l] * blk * sizeof(double));
+    p.off_ngram.push_back(off);
+    off = align256(off + (size_t)p.pairs[l] * blk * sizeof(double));
   }
   p.total = off;
   return p;
@@ -617,6 +917,8 @@ hipError_t tsqr_run(hipStream_t st, int64_t n, int d, int leaf_rows, const T* Y,
   T* work = reinterpret_cast<T*>(base + p.off_work);
   T* tau = reinterpret_cast<T*>(base + p.off_tau);
   T* tm = reinterpret_cast<T*>(base + p.off_t);
+  T* tbig = reinterpret_cast<T*>(base + p.off_tbig);
+  T* gram = reinterpret_cast<T*>(base + p.off_gram);
   const QrShape ls = qr_shape<T>(leaf_rows, p.m_last, p.nleaf, d);
   const int64_t lstride = (int64_t)leaf_rows * d;
   const int64_t dd = (int64_t)d * d;
@@ -624,7 +926,7 @@ hipError_t tsqr_run(hipStream_t st, int64_t n, int d, int leaf_rows, const T* Y,
 
   // Eq. (1): leaf QRs on a working copy of Y.
   LR_TRY(launch_copy<T>(st, Y, work, n * d));
-  LR_TRY(batched_qr<T>(st, work, lstride, ls, tau, tm));
+  LR_TRY(batched_qr<T>(st, work, lstride, ls, tau, tm, tbig, gram));
   double* r0 = reinterpret_cast<double*>(base + p.off_r[0]);
   hipLaunchKernelGGL(extract_r_kernel<T>, dim3(ddblocks, p.nleaf), dim3(256), 0, st, work, lstride, d, d, r0,
                      p.nleaf);
@@ -639,9 +941,11 @@ hipError_t tsqr_run(hipStream_t st, int64_t n, int d, int leaf_rows, const T* Y,
     double* node = reinterpret_cast<double*>(base + p.off_node[l]);
     double* ntau = reinterpret_cast<double*>(base + p.off_ntau[l]);
     double* nt = reinterpret_cast<double*>(base + p.off_nt[l]);
+    double* ntbig = reinterpret_cast<double*>(base + p.off_ntbig[l]);
+    double* ngram = reinterpret_cast<double*>(base + p.off_ngram[l]);
     const QrShape ns = qr_shape<double>(2 * d, 2 * d, np, d, true);
     LR_TRY(launch_copy<double>(st, rin, node, (int64_t)np * 2 * dd));  // pairs are adjacent in rin
-    LR_TRY(batched_qr<double>(st, node, 2 * dd, ns, ntau, nt));
+    LR_TRY(batched_qr<double>(st, node, 2 * dd, ns, ntau, nt, ntbig, ngram));
     hipLaunchKernelGGL(extract_r_kernel<double>, dim3(ddblocks, np), dim3(256), 0, st, node, 2 * dd, d, d, rout, np);
     LR_TRY(hipGetLastError());
     if (p.count[l] % 2 == 1)
@@ -660,14 +964,14 @@ hipError_t tsqr_run(hipStream_t st, int64_t n, int d, int leaf_rows, const T* Y,
     double* mup = reinterpret_cast<double*>(base + p.off_m[l + 1]);
     double* mdn = reinterpret_cast<double*>(base + p.off_m[l]);
     double* node = reinterpret_cast<double*>(base + p.off_node[l]);
-    double* nt = reinterpret_cast<double*>(base + p.off_nt[l]);
+    double* ntbig = reinterpret_cast<double*>(base + p.off_ntbig[l]);
     const QrShape ns = qr_shape<double>(2 * d, 2 * d, np, d, true);
     // [M_up[k]; 0] into the pair slot (2k, 2k+1) of this level
     const unsigned b2 = (unsigned)((2 * dd + 255) / 256);
     hipLaunchKernelGGL(init_qblock_kernel<double>, dim3(b2, np), dim3(256), 0, st, mup, mdn, 2 * dd, 2 * d, 2 * d,
                        np, d);
     LR_TRY(hipGetLastError());
-    LR_TRY(batched_apply_q<double>(st, node, 2 * dd, mdn, 2 * dd, ns, nt));
+    LR_TRY(batched_apply_q<double>(st, node, 2 * dd, mdn, 2 * dd, ns, ntbig));
     if (p.count[l] % 2 == 1)
       LR_TRY(launch_copy<double>(st, mup + (int64_t)np * dd, mdn + (int64_t)(p.count[l] - 1) * dd, dd));
   }
@@ -678,7 +982,7 @@ hipError_t tsqr_run(hipStream_t st, int64_t n, int d, int leaf_rows, const T* Y,
   hipLaunchKernelGGL(init_qblock_kernel<T>, dim3(lb, p.nleaf), dim3(256), 0, st, m0, Q, lstride, leaf_rows,
                      p.m_last, p.nleaf, d);
   LR_TRY(hipGetLastError());
-  LR_TRY(batched_apply_q<T>(st, work, lstride, Q, lstride, ls, tm));
+  LR_TRY(batched_apply_q<T>(st, work, lstride, Q, lstride, ls, tbig));
   return hipSuccess;
 }
 
