@@ -24,33 +24,72 @@ namespace lr {
 constexpr int kUpdThreads = 256;
 constexpr int kUpdCols = 64;
 
-// Sum of NV values over the TPB-thread block; every thread gets the totals.
-// Each wave reduces with DPP moves, the first wave adds the wave partials in a
-// fixed order, and every thread reads the NV totals (two barriers).
+// Sum of NV values (NV a power of two <= 16) over the TPB-thread block; every
+// thread gets the totals. Inside each 16-lane row a transpose reduction halves
+// the vector at every DPP exchange (partners: half-row mirror, xor 8, xor 2,
+// xor 1), so after log2(NV) exchanges each lane holds the row sum of one value
+// and the remaining exchanges finish the row; the 4 row sums of every wave go
+// through LDS and NV threads add them in a fixed order (two barriers).
+template <typename T, int NV>
+__device__ __forceinline__ T row_exchange(T x, int stage) {
+  // stage 0: half-row mirror (l <-> 7 - l within each 8), 1: xor 8, 2: xor 2, 3: xor 1
+  if (stage == 0) return dpp_move<0x141>(x);
+  if (stage == 1) return dpp_move<0x128>(x);
+  if (stage == 2) return dpp_move<0x4E>(x);
+  return dpp_move<0xB1>(x);
+}
+
 template <typename T, int NV, int TPB>
 __device__ __forceinline__ void block_sum_vec(T (&v)[NV], int nvalid, T* red, T* res) {
+  static_assert(NV == 1 || NV == 2 || NV == 4 || NV == 8 || NV == 16, "NV must be a power of two <= 16");
   constexpr int NW = TPB / 64;
+  constexpr int LOG = NV == 1 ? 0 : NV == 2 ? 1 : NV == 4 ? 2 : NV == 8 ? 3 : 4;
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
+  // lane bit that decides which half is kept at each transpose stage
+  const int kbit[4] = {(lane >> 2) & 1, (lane >> 3) & 1, (lane >> 1) & 1, lane & 1};
+  int idx = 0;
+  static_for<0, LOG>([&](auto ss) {
+    constexpr int S = decltype(ss)::value;
+    constexpr int H = NV >> (S + 1);  // half length at this stage
+    const bool hi = kbit[S] != 0;
 #pragma unroll
-  for (int i = 0; i < NV; ++i)
-    if (i < nvalid) v[i] = wave_sum(v[i]);
-  if (lane == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i)
-      if (i < nvalid) red[w * NV + i] = v[i];
+    for (int i = 0; i < H; ++i) {
+      const T mine = hi ? v[H + i] : v[i];
+      const T other = hi ? v[i] : v[H + i];
+      v[i] = mine + row_exchange<T, NV>(other, S);
+    }
+    idx += hi ? H : 0;
+  });
+  // remaining exchanges: plain sums of the single kept value
+  if constexpr (NV == 1) {
+    // order xor 1, xor 2, mirror, xor 8 (mirror pairs whole quads once the quads agree)
+    v[0] += row_exchange<T, NV>(v[0], 3);
+    v[0] += row_exchange<T, NV>(v[0], 2);
+    v[0] += row_exchange<T, NV>(v[0], 0);
+    v[0] += row_exchange<T, NV>(v[0], 1);
+  } else {
+    static_for<LOG, 4>([&](auto ss) {
+      constexpr int S = decltype(ss)::value;
+      v[0] += row_exchange<T, NV>(v[0], S);
+    });
   }
+  // lanes whose unused bits are zero write their row's sum of value idx
+  const int row = lane >> 4;
+  bool writer = true;
+#pragma unroll
+  for (int st = LOG; st < 4; ++st) writer = writer && (kbit[st] == 0);
+  if (writer) red[(w * 4 + row) * NV + idx] = v[0];
   __syncthreads();
   if ((int)threadIdx.x < nvalid) {
-    T s = 0;
+    T sum = 0;
 #pragma unroll
-    for (int k = 0; k < NW; ++k) s += red[k * NV + threadIdx.x];
-    res[threadIdx.x] = s;
+    for (int k = 0; k < NW * 4; ++k) sum += red[k * NV + threadIdx.x];
+    res[threadIdx.x] = sum;
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < NV; ++i)
-    if (i < nvalid) v[i] = res[i];
+  for (int i = 0; i < NV; ++i) v[i] = (i < nvalid) ? res[i] : (T)0;
 }
 
 // Rows a panel touches. Plain mode: rows p0 .. m-1. Tree mode (tree_d = d > 0,
@@ -86,7 +125,7 @@ __global__ __launch_bounds__(TPB) void panel_factor_kernel(T* __restrict__ A, in
                                                                      int tree_d, T* __restrict__ tau_all,
                                                                      int64_t tau_bstride, T* __restrict__ tmat,
                                                                      int64_t t_bstride) {
-  __shared__ T red[(TPB / 64) * NB];
+  __shared__ T red[(TPB / 64) * 4 * NB];
   __shared__ T res[NB];
   __shared__ T s_alpha[NB];
   __shared__ T s_tau[NB];
@@ -210,7 +249,7 @@ __global__ __launch_bounds__(TPB) void panel_factor_kernel(T* __restrict__ A, in
 
 // B[rows, cols] <- (I - V T' V^T) B[rows, cols], T' = T^T (TRANS) or T, over the
 // rows of the panel's row map. V occupies columns [p0, p0 + NB) of Vmat (unit
-// diagonal, zeros above). A 256-thread workgroup owns 64 columns; each thread
+// diagonal, zeros above). A 256-thread workgroup owns UC (16 or 64) columns; each thread
 // owns 16 bytes of consecutive columns (CPT = 4 floats or 2 doubles) so every
 // load keeps a full 16-byte request in flight; row groups are combined by
 // cross-lane shuffles and the 4 wave partials in LDS. V is staged through LDS
@@ -230,7 +269,7 @@ struct Vec16<double> {
   static constexpr int n = 2;
 };
 
-template <typename T, int NB, bool TRANS>
+template <typename T, int NB, bool TRANS, int UC>
 __global__ __launch_bounds__(kUpdThreads) void panel_apply_kernel(const T* Vmat, int64_t vstride, T* Bmat,
                                                                   int64_t bstride, int m_full, int m_last,
                                                                   int nbatch, int ld, int p0, int nbw, int tree_d,
@@ -238,12 +277,12 @@ __global__ __launch_bounds__(kUpdThreads) void panel_apply_kernel(const T* Vmat,
                                                                   const T* __restrict__ tmat, int64_t t_bstride) {
   using VT = typename Vec16<T>::type;
   constexpr int CPT = Vec16<T>::n;         // columns per thread
-  constexpr int TPR = kUpdCols / CPT;      // threads per row
+  constexpr int TPR = UC / CPT;      // threads per row
   constexpr int RG = kUpdThreads / TPR;    // row groups
   constexpr int RGW = 64 / TPR;            // row groups per wave
   __shared__ T vch[kApplyChunk][NB];
-  __shared__ T red[4][NB][kUpdCols];
-  __shared__ T wsh[NB][kUpdCols];
+  __shared__ T red[4][NB][UC];
+  __shared__ T wsh[NB][UC];
   __shared__ T Ts[NB * NB];
 
   const int b = blockIdx.y;
@@ -257,7 +296,7 @@ __global__ __launch_bounds__(kUpdThreads) void panel_apply_kernel(const T* Vmat,
   const int lane = t & 63;
   const int tc = t % TPR;
   const int rg = t / TPR;
-  const int cbase = col_begin + blockIdx.x * kUpdCols;
+  const int cbase = col_begin + blockIdx.x * UC;
   const int col0 = cbase + tc * CPT;
   // vector access needs every column of the vector present and 16-byte alignment
   const bool vec_ok = (col0 + CPT <= col_end) && (((int64_t)ld * sizeof(T)) % 16 == 0) && (col0 % CPT == 0);
@@ -328,7 +367,7 @@ __global__ __launch_bounds__(kUpdThreads) void panel_apply_kernel(const T* Vmat,
       for (int q = 0; q < CPT; ++q) red[w][i][tc * CPT + q] = acc[i][q];
   }
   __syncthreads();
-  if (t < kUpdCols) {
+  if (t < UC) {
     T wv[NB];
 #pragma unroll
     for (int i = 0; i < NB; ++i) wv[i] = red[0][i][t] + red[1][i][t] + red[2][i][t] + red[3][i][t];
@@ -749,14 +788,22 @@ static hipError_t launch_panel_factor_nb(hipStream_t st, int rpt, T* A, int64_t 
   }
 }
 
+// Narrow updates (at most 64 columns, the inner panels inside an outer panel)
+// take 16-column workgroups, so a batch of a few matrices still fills the chip.
 template <typename T, int NB, bool TRANS>
 static hipError_t launch_apply_nb(hipStream_t st, const T* V, int64_t vstride, T* B, int64_t bstride,
                                   const QrShape& s, int p0, int nbw, int c0, int c1, const T* tm) {
   if (c1 <= c0) return hipSuccess;
-  const int ncb = (c1 - c0 + kUpdCols - 1) / kUpdCols;
-  hipLaunchKernelGGL((panel_apply_kernel<T, NB, TRANS>), dim3(ncb, s.nbatch), dim3(kUpdThreads), 0, st, V, vstride,
-                     B, bstride, s.m_full, s.m_last, s.nbatch, s.d, p0, nbw, s.tree_d, c0, c1, tm,
-                     (int64_t)s.npanels * NB * NB);
+  const int64_t tbs = (int64_t)s.npanels * NB * NB;
+  if (c1 - c0 <= 64) {
+    const int ncb = (c1 - c0 + 15) / 16;
+    hipLaunchKernelGGL((panel_apply_kernel<T, NB, TRANS, 16>), dim3(ncb, s.nbatch), dim3(kUpdThreads), 0, st, V,
+                       vstride, B, bstride, s.m_full, s.m_last, s.nbatch, s.d, p0, nbw, s.tree_d, c0, c1, tm, tbs);
+  } else {
+    const int ncb = (c1 - c0 + kUpdCols - 1) / kUpdCols;
+    hipLaunchKernelGGL((panel_apply_kernel<T, NB, TRANS, kUpdCols>), dim3(ncb, s.nbatch), dim3(kUpdThreads), 0, st,
+                       V, vstride, B, bstride, s.m_full, s.m_last, s.nbatch, s.d, p0, nbw, s.tree_d, c0, c1, tm, tbs);
+  }
   return hipGetLastError();
 }
 
