@@ -477,7 +477,7 @@ __device__ __forceinline__ void load4(const T* src, int c0, int cend, bool vec, 
 // V = columns [P0, P0 + W) of Vmat with unit diagonal and zeros above, over the
 // rows of the outer panel's row map; B columns [col_begin, col_end).
 template <typename T, int MODE>
-__global__ __launch_bounds__(kBlkThreads) void block_apply_kernel(const T* Vmat, int64_t vstride, T* Bmat,
+__global__ __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) void block_apply_kernel(const T* Vmat, int64_t vstride, T* Bmat,
                                                                   int64_t bstride, int m_full, int m_last,
                                                                   int nbatch, int ld, int P0, int W, int tree_d,
                                                                   int col_begin, int col_end,
@@ -520,6 +520,34 @@ __global__ __launch_bounds__(kBlkThreads) void block_apply_kernel(const T* Vmat,
     }
   };
 
+  // Interior rows (compact index >= kOuter, below every reflector's unit
+  // diagonal, and < nact) of a full-width block take unmasked 16-byte loads;
+  // the first kOuter rows and the ragged end take the masked path.
+  const bool fast = vec_v && vec_b && (W == kOuter) && (cb0 + kOuter <= cend);
+  const int nint = nact & ~15;  // rows [kOuter, nint) are interior
+  auto vrow4_fast = [&](int ci, int q, T (&x)[4]) {
+    const T* src = V + (int64_t)rm.row(ci) * ld + P0 + 4 * q;
+    if constexpr (sizeof(T) == 4) {
+      const float4 v = *reinterpret_cast<const float4*>(src);
+      x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+    } else {
+      const double2 u = *reinterpret_cast<const double2*>(src);
+      const double2 v = *reinterpret_cast<const double2*>(src + 2);
+      x[0] = u.x; x[1] = u.y; x[2] = v.x; x[3] = v.y;
+    }
+  };
+  auto brow4_fast = [&](int ci, int q, T (&x)[4]) {
+    const T* src = B + (int64_t)rm.row(ci) * ld + cb0 + 4 * q;
+    if constexpr (sizeof(T) == 4) {
+      const float4 v = *reinterpret_cast<const float4*>(src);
+      x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+    } else {
+      const double2 u = *reinterpret_cast<const double2*>(src);
+      const double2 v = *reinterpret_cast<const double2*>(src + 2);
+      x[0] = u.x; x[1] = u.y; x[2] = v.x; x[3] = v.y;
+    }
+  };
+
   // ---- pass 1: W = V^T B (tile (ti, tj) entry (r, c) is W[4r + ti][4c + tj])
   Acc acc[4][4];
 #pragma unroll
@@ -528,7 +556,7 @@ __global__ __launch_bounds__(kBlkThreads) void block_apply_kernel(const T* Vmat,
     for (int c = 0; c < 4; ++c)
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc[a][c][e] = 0;
-  for (int r0 = 4 * w; r0 < nact; r0 += 16) {
+  auto quad_masked = [&](int r0) {
     const int ci = r0 + lg;
     T va[4], vb[4];
     vrow4(ci, l15, va);
@@ -545,6 +573,46 @@ __global__ __launch_bounds__(kBlkThreads) void block_apply_kernel(const T* Vmat,
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[a][c] = M::step(va[a], vb[c], acc[a][c]);
+  };
+  int r0 = 4 * w;
+  const int head_end = fast ? kOuter : nact;
+  for (; r0 < head_end && r0 < nact; r0 += 16) quad_masked(r0);
+  if (fast) {
+    // four row quads per trip; the next trip's loads are issued before this
+    // trip's products (two register sets, trips in pairs). Rows of a trip past
+    // the interior are clamped to the last interior quad and multiply nothing.
+    // trip k reads rows r0 + 64 k .. r0 + 64 k + 51, all below nint
+    const int ntrip = (nint - r0 >= 52) ? (nint - r0 - 52) / 64 + 1 : 0;
+    auto load_trip = [&](int k, T (&va)[4][4], T (&vb)[4][4]) {
+      const int rb = r0 + 64 * (k < ntrip ? k : ntrip - 1);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        vrow4_fast(rb + 16 * u + lg, l15, va[u]);
+        if (MODE != 2) brow4_fast(rb + 16 * u + lg, l15, vb[u]);
+      }
+    };
+    auto mma_trip = [&](const T (&va)[4][4], const T (&vb)[4][4]) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[a][c] = M::step(va[u][a], MODE == 2 ? va[u][c] : vb[u][c], acc[a][c]);
+    };
+    if (ntrip > 0) {
+      T va0[4][4], vb0[4][4], va1[4][4], vb1[4][4];
+      load_trip(0, va0, vb0);
+      int k = 0;
+      for (; k + 1 < ntrip; k += 2) {
+        load_trip(k + 1, va1, vb1);
+        mma_trip(va0, vb0);
+        load_trip(k + 2, va0, vb0);
+        mma_trip(va1, vb1);
+      }
+      if (k < ntrip) mma_trip(va0, vb0);
+      r0 += 64 * ntrip;
+    }
+    for (; r0 < nact; r0 += 16) quad_masked(r0);
   }
   // combine the 4 waves' partial sums in LDS, one wave after the other
   for (int ww = 0; ww < 4; ++ww) {
@@ -602,14 +670,29 @@ __global__ __launch_bounds__(kBlkThreads) void block_apply_kernel(const T* Vmat,
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int tc = 0; tc < 4; ++tc) wb[q][u][tc] = Ws[16 * q + 4 * lg + u][16 * tc + l15];
-  for (int c0 = 16 * w; c0 < nact; c0 += 64) {
+  auto chunk = [&](int c0, auto fast_tag) {
+    constexpr bool FAST = decltype(fast_tag)::value;
     T va[4][4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       T x[4];
-      vrow4(c0 + l15, 4 * q + lg, x);
+      if constexpr (FAST) {
+        vrow4_fast(c0 + l15, 4 * q + lg, x);
+      } else {
+        vrow4(c0 + l15, 4 * q + lg, x);
+      }
 #pragma unroll
       for (int u = 0; u < 4; ++u) va[q][u] = x[u];
+    }
+    // the B entries this lane updates, requested before the products
+    T bold[4][4];
+    if constexpr (FAST) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const T* src = B + (int64_t)rm.row(c0 + acc_row<Acc>(lg, e)) * ld + cb0 + l15;
+#pragma unroll
+        for (int tc = 0; tc < 4; ++tc) bold[e][tc] = src[16 * tc];
+      }
     }
     Acc out[4];
 #pragma unroll
@@ -625,13 +708,70 @@ __global__ __launch_bounds__(kBlkThreads) void block_apply_kernel(const T* Vmat,
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int ci = c0 + acc_row<Acc>(lg, e);
-      if (ci < nact) {
+      if (FAST) {
+        T* dst = B + (int64_t)rm.row(ci) * ld + cb0 + l15;
+#pragma unroll
+        for (int tc = 0; tc < 4; ++tc) dst[16 * tc] = bold[e][tc] - out[tc][e];
+      } else if (ci < nact) {
         T* dst = B + (int64_t)rm.row(ci) * ld + cb0 + l15;
 #pragma unroll
         for (int tc = 0; tc < 4; ++tc)
           if (cb0 + 16 * tc + l15 < cend) dst[16 * tc] -= out[tc][e];
       }
     }
+  };
+  int c0 = 16 * w;
+  for (; c0 < (fast ? kOuter : nact) && c0 < nact; c0 += 64) chunk(c0, std::false_type{});
+  if (fast) {
+    // interior chunks: the next chunk's V rows and B entries are loaded before
+    // this chunk's products (two register sets, chunks in pairs; the load past
+    // the last chunk re-reads it and is unused)
+    const int nch = (nint - c0 >= 16) ? (nint - c0 - 16) / 64 + 1 : 0;
+    auto load_chunk = [&](int k, T (&va)[4][4], T (&bo)[4][4]) {
+      const int cc = c0 + 64 * (k < nch ? k : nch - 1);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) vrow4_fast(cc + l15, 4 * q + lg, va[q]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const T* src = B + (int64_t)rm.row(cc + acc_row<Acc>(lg, e)) * ld + cb0 + l15;
+#pragma unroll
+        for (int tc = 0; tc < 4; ++tc) bo[e][tc] = src[16 * tc];
+      }
+    };
+    auto run_chunk = [&](int k, const T (&va)[4][4], const T (&bo)[4][4]) {
+      const int cc = c0 + 64 * k;
+      Acc out[4];
+#pragma unroll
+      for (int tc = 0; tc < 4; ++tc)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[tc][e] = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int tc = 0; tc < 4; ++tc) out[tc] = M::step(va[q][u], wb[q][u][tc], out[tc]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        T* dst = B + (int64_t)rm.row(cc + acc_row<Acc>(lg, e)) * ld + cb0 + l15;
+#pragma unroll
+        for (int tc = 0; tc < 4; ++tc) dst[16 * tc] = bo[e][tc] - out[tc][e];
+      }
+    };
+    if (nch > 0) {
+      T va0[4][4], bo0[4][4], va1[4][4], bo1[4][4];
+      load_chunk(0, va0, bo0);
+      int k = 0;
+      for (; k + 1 < nch; k += 2) {
+        load_chunk(k + 1, va1, bo1);
+        run_chunk(k, va0, bo0);
+        load_chunk(k + 2, va0, bo0);
+        run_chunk(k + 1, va1, bo1);
+      }
+      if (k < nch) run_chunk(k, va0, bo0);
+      c0 += 64 * nch;
+    }
+    for (; c0 < nact; c0 += 64) chunk(c0, std::false_type{});
   }
 }
 
