@@ -155,6 +155,148 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(int64_t n, int64_t chunk, 
       }
 }
 
+// Fast path of the same product for X a transposed dense Omega (float or bf16
+// bits, 8 consecutive rows of a column in one 16-byte load) and Y a row-major
+// float matrix (4 consecutive columns in one 16-byte load). A workgroup owns
+// a 64 x 128 block of the output, each wave 32 x 64: its 4 column tiles take
+// the columns j0 + 4 l + t (l = lane mod 16, t = tile), so every lane loads
+// whole 16-byte rows of Y. Steps of 32 rows run in pairs with two register
+// sets, the next step's loads issued before the current step's 64 products;
+// float accumulators are added to float64 ones every kTnFlushSteps steps.
+template <int XDT>
+__global__ __launch_bounds__(256) void gemm_tn_xt_kernel(int64_t n, int64_t chunk, int M, int N,
+                                                         const void* __restrict__ xptr, int64_t xld,
+                                                         const float* __restrict__ Y, int64_t yld,
+                                                         double* __restrict__ partial) {
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int fl = lane & 15, fg = lane >> 4;
+  const int i0 = blockIdx.x * 64 + (w & 1) * 32;
+  const int j0 = blockIdx.y * 128 + (w >> 1) * 64;
+  const int64_t rbeg = (int64_t)blockIdx.z * chunk;
+  int64_t rend = rbeg + chunk;
+  if (rend > n) rend = n;
+
+  f32x4_t acc[2][4];
+  double acc64[2][4][4];
+#pragma unroll
+  for (int f = 0; f < 2; ++f)
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        acc[f][t][q] = 0.0f;
+        acc64[f][t][q] = 0.0;
+      }
+  struct Step {
+    float x[2][8];
+    float y[8][4];
+  };
+  // rows r0 + 8 fg + e; FULL: all 32 rows < rend
+  auto load_step = [&](int64_t r0, Step& st, bool full) {
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      const int64_t col = i0 + 16 * f + fl;
+      const int64_t rr = r0 + 8 * fg;
+      // a group starting below rend ends inside the column (rr and ld are
+      // multiples of 8 and ld >= n); a group starting at or past rend is zero
+      if (!full && rr >= rend) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) st.x[f][e] = 0.0f;
+        continue;
+      }
+      if constexpr (XDT == 2) {
+        const uint16_t* src = static_cast<const uint16_t*>(xptr) + col * xld + rr;
+        uint4 raw = *reinterpret_cast<const uint4*>(src);
+        const uint32_t wv[4] = {raw.x, raw.y, raw.z, raw.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          st.x[f][2 * q] = __uint_as_float(wv[q] << 16);
+          st.x[f][2 * q + 1] = __uint_as_float(wv[q] & 0xffff0000u);
+        }
+      } else {
+        const float* src = static_cast<const float*>(xptr) + col * xld + rr;
+        const float4 a = *reinterpret_cast<const float4*>(src);
+        const float4 b = *reinterpret_cast<const float4*>(src + 4);
+        st.x[f][0] = a.x; st.x[f][1] = a.y; st.x[f][2] = a.z; st.x[f][3] = a.w;
+        st.x[f][4] = b.x; st.x[f][5] = b.y; st.x[f][6] = b.z; st.x[f][7] = b.w;
+      }
+      if (!full) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          if (rr + e >= rend) st.x[f][e] = 0.0f;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t r = r0 + 8 * fg + e;
+      if (full || r < rend) {
+        const float4 v = *reinterpret_cast<const float4*>(Y + r * yld + j0 + 4 * fl);
+        st.y[e][0] = v.x; st.y[e][1] = v.y; st.y[e][2] = v.z; st.y[e][3] = v.w;
+      } else {
+        st.y[e][0] = st.y[e][1] = st.y[e][2] = st.y[e][3] = 0.0f;
+      }
+    }
+  };
+  auto mma_step = [&](const Step& st) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+#pragma unroll
+      for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          acc[f][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(st.x[f][e], st.y[e][t], acc[f][t], 0, 0, 0);
+  };
+  auto flush = [&]() {
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          acc64[f][t][q] += (double)acc[f][t][q];
+          acc[f][t][q] = 0.0f;
+        }
+  };
+
+  const int64_t nfull = (rend - rbeg) / 32;  // complete steps
+  int64_t k = 0;
+  if (nfull > 0) {
+    Step s0, s1;
+    // the load past the last complete step re-reads it and is unused
+    auto rowk = [&](int64_t kk) { return rbeg + 32 * (kk < nfull ? kk : nfull - 1); };
+    load_step(rowk(0), s0, true);
+    for (; k + 1 < nfull; k += 2) {
+      load_step(rowk(k + 1), s1, true);
+      mma_step(s0);
+      load_step(rowk(k + 2), s0, true);
+      mma_step(s1);
+      if ((k / 2) % (kTnFlushSteps / 2) == kTnFlushSteps / 2 - 1) flush();
+    }
+    if (k < nfull) {
+      mma_step(s0);
+      ++k;
+    }
+  }
+  if (rbeg + 32 * k < rend) {  // ragged last step
+    Step s2;
+    load_step(rbeg + 32 * k, s2, false);
+    mma_step(s2);
+  }
+  flush();
+  double* out = partial + (int64_t)blockIdx.z * M * N;
+#pragma unroll
+  for (int f = 0; f < 2; ++f)
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = i0 + 16 * f + acc_row<f32x4_t>(fg, q);
+        const int col = j0 + 4 * fl + t;
+        out[(int64_t)row * N + col] = acc64[f][t][q];
+      }
+}
+
 __global__ void fill_kernel(double* __restrict__ out, int64_t count, double v) {
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (idx < count) out[idx] = v;
@@ -206,6 +348,24 @@ hipError_t launch_gemm_tn(hipStream_t st, int64_t n, int M, int N, const TnOpera
   const int64_t chunk = tn_chunk(n);
   const int64_t nch = (n + chunk - 1) / chunk;
   double* partial = static_cast<double*>(ws);
+  // fast path: transposed float/bf16 Omega against a row-major float matrix
+  const bool y16 = Y.kind == 0 && Y.dtype == 1 && Y.ld % 4 == 0 && reinterpret_cast<uintptr_t>(Y.ptr) % 16 == 0;
+  const bool x16 = X.kind == 1 && (X.dtype == 1 || X.dtype == 2) && X.ld % 8 == 0 &&
+                   reinterpret_cast<uintptr_t>(X.ptr) % 16 == 0;
+  if (!f64 && x16 && y16 && M % 64 == 0 && N % 128 == 0) {
+    dim3 g2(M / 64, N / 128, (unsigned)nch);
+    if (X.dtype == 2)
+      hipLaunchKernelGGL(gemm_tn_xt_kernel<2>, g2, dim3(256), 0, st, n, chunk, M, N, X.ptr, X.ld,
+                         static_cast<const float*>(Y.ptr), Y.ld, partial);
+    else
+      hipLaunchKernelGGL(gemm_tn_xt_kernel<1>, g2, dim3(256), 0, st, n, chunk, M, N, X.ptr, X.ld,
+                         static_cast<const float*>(Y.ptr), Y.ld, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, partial,
+                       nch, count, x_scale, out);
+    return hipGetLastError();
+  }
   dim3 grid((M + 63) / 64, (N + 63) / 64, (unsigned)nch);
   if (f64)
     hipLaunchKernelGGL(gemm_tn_kernel<double>, grid, dim3(256), 0, st, n, chunk, M, N, X, Y, partial);

@@ -135,3 +135,43 @@ def test_c3_full_bf16_pipeline_properties():
     note(f"  C3 X vs factor-recomputation {err:.2e}, logdet {sol.logdet.item():.6e}")
     assert err <= 1e-4
     assert math.isfinite(sol.logdet.item())
+
+
+@pytest.mark.parametrize("prec", ["bf16", "f32"])
+def test_omega_t_q_product_against_oracle(prec):
+    """F = Omega^T Q (the d x d cross product of the Woodbury core), read back
+    from the LU factors lr_lowrank_solve returns, against the FP64 product of
+    the same Omega values and the same float32 Q. Ragged n (two full row
+    chunks of 4096 plus 40 rows) so every row path of the product is taken.
+    Bound: float32 partial sums of at most 512 terms (then float64), i.e.
+    gamma_512 u32 relative to sum_r |Omega_ri| |Q_rj|."""
+    dev = device()
+    a = api()
+    n, d, m = 8232, 128, 3
+    rng = np.random.default_rng(31)
+    q = np.linalg.qr(rng.standard_normal((n, d)))[0].astype(np.float32)
+    r = np.triu(rng.standard_normal((d, d)), 1) + np.diag(1.0 + np.abs(rng.standard_normal(d)))
+    w = W.small(W.WORKLOADS["C3"], n, d=d, m=m)
+    om_np, om = omega_pair(w, prec, dev)
+    A = rng.standard_normal((n, m)).astype(np.float32)
+    note(f"Omega^T Q product n={n} d={d} prec={prec}")
+    sol = a.lowrank_solve(to_dev(q, torch.float32, dev), to_dev(r, torch.float64, dev), om, prec, w.sigma2,
+                          to_dev(A, torch.float32, dev))
+    torch.cuda.synchronize()
+    # random Q, R need not give a positive definite core (info > 0 from the
+    # Cholesky); the LU factors of F are written before it (info < 0 would be
+    # a zero pivot of F)
+    assert int(sol.info.item()) >= 0
+    flu = sol.Flu.cpu().numpy()
+    piv = sol.piv.cpu().numpy()
+    f = (np.tril(flu, -1) + np.eye(d)) @ np.triu(flu)
+    for k in range(d - 1, -1, -1):  # undo the row exchanges, last first
+        p = int(piv[k])
+        f[[k, p]] = f[[p, k]]
+    om_t = om_np["omega_t"].astype(np.float64)
+    q64 = q.astype(np.float64)
+    ref = om_t @ q64
+    scale = np.abs(om_t) @ np.abs(q64)
+    err = float((np.abs(f - ref) / scale).max())
+    note(f"  max |F - Omega^T Q| / (|Omega|^T |Q|) = {err:.3e}")
+    assert err <= 520 * 2.0 ** -24
