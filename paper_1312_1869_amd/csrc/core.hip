@@ -40,11 +40,27 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // A22 -= L21 U12 (L21 staged through LDS).
 constexpr int kPanel = 32;
 
+template <int CTRL>
+__device__ __forceinline__ void argmax_dpp(double& a, int& i) {
+  const double oa = dpp_move<CTRL>(a);
+  const int oi = __builtin_amdgcn_update_dpp(0, i, CTRL, 0xF, 0xF, false);
+  if (oa > a || (oa == a && oi < i)) {
+    a = oa;
+    i = oi;
+  }
+}
+
 __device__ __forceinline__ int block_argmax_db(double v, int idx, double* redv, int* redi, int& parity) {
   double a = v;
   int i = idx;
+  // inside each 16-lane row by DPP (xor 1, xor 2, half-row mirror, xor 8),
+  // then across the 4 rows by two lane shuffles
+  argmax_dpp<0xB1>(a, i);
+  argmax_dpp<0x4E>(a, i);
+  argmax_dpp<0x141>(a, i);
+  argmax_dpp<0x128>(a, i);
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
+  for (int off = 16; off <= 32; off <<= 1) {
     const double oa = __shfl_xor(a, off, 64);
     const int oi = __shfl_xor(i, off, 64);
     if (oa > a || (oa == a && oi < i)) {

@@ -229,20 +229,21 @@ __global__ __launch_bounds__(TPB) void panel_factor_kernel(T* __restrict__ A, in
         if (c < nbw) M[roff + c] = a[k][c];
     }
   }
-  // T (upper triangular, LDS): T[c][c] = tau_c, T[0:c, c] = -tau_c T[0:c, 0:c] y_c
-  if (t == 0) {
-    for (int i = 0; i < NB * NB; ++i) s_t[i] = 0;
-    for (int c = 0; c < nbw; ++c) {
-      const T tc = s_tau[c];
-      for (int r = 0; r < c; ++r) {
-        T s = 0;
-        for (int q = r; q < c; ++q) s += s_t[r * NB + q] * s_y[c * NB + q];
-        s_t[r * NB + c] = -tc * s;
-      }
+  // T (upper triangular, LDS): T[c][c] = tau_c, T[0:c, c] = -tau_c T[0:c, 0:c] y_c,
+  // column by column, the entries of a column in parallel (thread r < c)
+  if (t < NB * NB) s_t[t] = 0;
+  __syncthreads();
+  for (int c = 0; c < nbw; ++c) {
+    const T tc = s_tau[c];
+    if (t < c) {
+      T s = 0;
+      for (int q = t; q < c; ++q) s += s_t[t * NB + q] * s_y[c * NB + q];
+      s_t[t * NB + c] = -tc * s;
+    } else if (t == c) {
       s_t[c * NB + c] = tc;
     }
+    __syncthreads();
   }
-  __syncthreads();
   if (t < NB * NB) tmat[(int64_t)b * t_bstride + t] = s_t[t];
   if (t < nbw) tau_all[(int64_t)b * tau_bstride + p0 + t] = s_tau[t];
 }
