@@ -253,9 +253,8 @@ __global__ __launch_bounds__(TPB) void panel_factor_kernel(T* __restrict__ A, in
 // diagonal, zeros above). A 256-thread workgroup owns UC (16 or 64) columns; each thread
 // owns 16 bytes of consecutive columns (CPT = 4 floats or 2 doubles) so every
 // load keeps a full 16-byte request in flight; row groups are combined by
-// cross-lane shuffles and the 4 wave partials in LDS. V is staged through LDS
-// in chunks of kApplyChunk rows.
-constexpr int kApplyChunk = 64;
+// cross-lane shuffles and the 4 wave partials in LDS. Every thread reads the
+// V rows of its own rows directly, so the row loops have no barriers.
 
 template <typename T>
 struct Vec16;
@@ -281,7 +280,6 @@ __global__ __launch_bounds__(kUpdThreads) void panel_apply_kernel(const T* Vmat,
   constexpr int TPR = UC / CPT;      // threads per row
   constexpr int RG = kUpdThreads / TPR;    // row groups
   constexpr int RGW = 64 / TPR;            // row groups per wave
-  __shared__ T vch[kApplyChunk][NB];
   __shared__ T red[4][NB][UC];
   __shared__ T wsh[NB][UC];
   __shared__ T Ts[NB * NB];
@@ -304,18 +302,25 @@ __global__ __launch_bounds__(kUpdThreads) void panel_apply_kernel(const T* Vmat,
 
   if (t < NB * NB) Ts[t] = tmat[(int64_t)b * t_bstride + t];
 
-  auto stage = [&](int c0) {
-    for (int e = t; e < kApplyChunk * NB; e += kUpdThreads) {
-      const int r = e / NB, i = e % NB;
-      const int ci = c0 + r;
-      T val = 0;
-      if (ci < nact && i < nbw) {
-        if (ci > i)
-          val = V[(int64_t)rm.row(ci) * ld + p0 + i];
-        else if (ci == i)
-          val = (T)1;
+  // V row ci (panel columns 0..NB-1) with the unit-lower mask; whole rows
+  // are read with 16-byte loads when aligned
+  const bool vvec = (((int64_t)ld * sizeof(T)) % 16 == 0) && (p0 % CPT == 0) &&
+                    (reinterpret_cast<uintptr_t>(V) % 16 == 0) && (NB % CPT == 0) && (nbw == NB);
+  auto vrow = [&](int ci, T (&v)[NB]) {
+    const T* src = V + (int64_t)rm.row(ci) * ld + p0;
+    if (vvec) {  // a full panel: the whole row segment lies inside the row
+#pragma unroll
+      for (int q = 0; q < NB / CPT; ++q) {
+        const VT x = *reinterpret_cast<const VT*>(src + q * CPT);
+        __builtin_memcpy(&v[q * CPT], &x, sizeof(VT));
       }
-      vch[r][i] = val;
+    } else {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) v[i] = (i < nbw) ? src[i] : (T)0;
+    }
+    if (ci < NB) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) v[i] = (i >= nbw) ? (T)0 : (ci > i ? v[i] : (ci == i ? (T)1 : (T)0));
     }
   };
   auto load_row = [&](int ci, T (&x)[CPT]) {
@@ -334,22 +339,17 @@ __global__ __launch_bounds__(kUpdThreads) void panel_apply_kernel(const T* Vmat,
   for (int i = 0; i < NB; ++i)
 #pragma unroll
     for (int q = 0; q < CPT; ++q) acc[i][q] = 0;
-  for (int c0 = 0; c0 < nact; c0 += kApplyChunk) {
-    stage(c0);
-    __syncthreads();
-    const int rend = min(kApplyChunk, nact - c0);
+  // no LDS staging: each thread reads the V rows it needs (shared by the TPR
+  // threads of a row through the caches), so the row loop has no barriers
 #pragma unroll 4
-    for (int r = rg; r < rend; r += RG) {
-      T x[CPT];
-      load_row(c0 + r, x);
+  for (int ci = rg; ci < nact; ci += RG) {
+    T v[NB], x[CPT];
+    vrow(ci, v);
+    load_row(ci, x);
 #pragma unroll
-      for (int i = 0; i < NB; ++i) {
-        const T vi = vch[r][i];
+    for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) acc[i][q] += vi * x[q];
-      }
-    }
-    __syncthreads();
+      for (int q = 0; q < CPT; ++q) acc[i][q] += v[i] * x[q];
   }
   // combine the row groups of each wave (lanes tc, tc + TPR, ...), then the waves
 #pragma unroll
@@ -395,32 +395,25 @@ __global__ __launch_bounds__(kUpdThreads) void panel_apply_kernel(const T* Vmat,
   for (int i = 0; i < NB; ++i)
 #pragma unroll
     for (int q = 0; q < CPT; ++q) wl[i][q] = wsh[i][tc * CPT + q];
-  for (int c0 = 0; c0 < nact; c0 += kApplyChunk) {
-    stage(c0);
-    __syncthreads();
-    const int rend = min(kApplyChunk, nact - c0);
 #pragma unroll 4
-    for (int r = rg; r < rend; r += RG) {
-      T x[CPT];
-      load_row(c0 + r, x);
+  for (int ci = rg; ci < nact; ci += RG) {
+    T v[NB], x[CPT];
+    vrow(ci, v);
+    load_row(ci, x);
 #pragma unroll
-      for (int i = 0; i < NB; ++i) {
-        const T vi = vch[r][i];
+    for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) x[q] -= vi * wl[i][q];
-      }
-      T* dst = B + (int64_t)rm.row(c0 + r) * ld + col0;
-      if (vec_ok) {
-        VT v;
-        __builtin_memcpy(&v, &x[0], sizeof(VT));
-        *reinterpret_cast<VT*>(dst) = v;
-      } else {
+      for (int q = 0; q < CPT; ++q) x[q] -= v[i] * wl[i][q];
+    T* dst = B + (int64_t)rm.row(ci) * ld + col0;
+    if (vec_ok) {
+      VT vv;
+      __builtin_memcpy(&vv, &x[0], sizeof(VT));
+      *reinterpret_cast<VT*>(dst) = vv;
+    } else {
 #pragma unroll
-        for (int q = 0; q < CPT; ++q)
-          if (col0 + q < col_end) dst[q] = x[q];
-      }
+      for (int q = 0; q < CPT; ++q)
+        if (col0 + q < col_end) dst[q] = x[q];
     }
-    __syncthreads();
   }
 }
 
