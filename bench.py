@@ -71,7 +71,7 @@ def source_hash(*files) -> str:
 def read_traffic(kernel_key: str, src_hash: str):
     """HBM bytes per launch from the committed counter summary, if it still
     describes the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "counters_sketch_dense_bf16_c3.txt")
+    path = os.path.join(ROOT, "profiles", "counters_sketch_bf16_c3_n262144_d512.txt")
     if not os.path.exists(path):
         return None
     kv = {}
