@@ -33,7 +33,8 @@
  *   - Precision `prec`: LR_PREC_F64 (all float64), LR_PREC_F32 (float32 kernel
  *     tiles, sketch and leaf QR; float64 tree, d x d core and solves),
  *     LR_PREC_BF16 (as F32, but the dense-Omega sketch rounds K tiles to
- *     bfloat16 and runs on bf16 matrix cores with float32 accumulation).
+ *     bfloat16 and runs on bf16 matrix cores with float32 accumulation;
+ *     n <= 2^25, else LR_ERR_UNSUPPORTED).
  *     "real" below means double for F64 and float otherwise.
  *   - Points X are float32 n x D (1 <= D <= 15) in every precision.
  *   - Sizes: n >= 1, 1 <= d <= 1024, d <= n, 0 <= m <= 64.

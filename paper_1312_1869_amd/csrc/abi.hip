@@ -62,6 +62,8 @@ lr_status check_omega(const lr_omega* o, int64_t n, int32_t d, int32_t prec) {
   if (o->kind == LR_OMEGA_GAUSS) {
     if (o->dense_t == nullptr || !aligned(o->dense_t, 16)) return LR_ERR_ARG;
     if (o->ld < n || o->ld % 8 != 0) return LR_ERR_SHAPE;
+    // the bf16 sketch addresses Omega through 31-bit buffer extents
+    if (prec == LR_PREC_BF16 && n > ((int64_t)1 << 25)) return LR_ERR_UNSUPPORTED;
     return LR_OK;
   }
   return LR_ERR_ARG;

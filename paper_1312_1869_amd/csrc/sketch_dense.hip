@@ -346,7 +346,7 @@ __global__ __launch_bounds__(512, 1) void sketch_dense_kernel(
 //   * the entries are rounded to bf16 and written to a double-buffered LDS
 //     tile in operand order; each wave reads the 8 row fragments of the tile
 //     and multiplies them with its WC Omega fragments (8 x WC products);
-//   * the Omega fragments of step s + 1 (two alternating register sets) and
+//   * the Omega fragments of step s + 2 (three rotating register sets) and
 //     the points of step s + 3 (three rotating sets) are requested at the
 //     start of step s.
 
@@ -380,6 +380,27 @@ __global__ void omega_frag_kernel(const uint16_t* __restrict__ omt, int64_t ld, 
   frag[q] = v;
 }
 
+// steps by which the bf16 sketch fetches its Omega fragments ahead
+#ifndef LR_B16_AHEAD
+#define LR_B16_AHEAD 2
+#endif
+constexpr int kB16Ahead = LR_B16_AHEAD;
+// interleave the kernel evaluation with the matrix-core operations
+#ifndef LR_B16_INTERLEAVE
+#define LR_B16_INTERLEAVE 1
+#endif
+constexpr bool kB16Interleave = LR_B16_INTERLEAVE != 0;
+
+// largest n of the bf16 matrix-core sketch (31-bit buffer extents)
+constexpr int64_t kBf16MaxRows = int64_t(1) << 25;
+
+// A raw buffer view of global memory: reads beyond `bytes` return zero.
+// The base is wave-uniform, so the view lives in scalar registers and each
+// load takes a 32-bit lane offset plus a scalar offset.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_view(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
 template <int E>
 __device__ __forceinline__ float row_bcast(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x150 + E, 0xF, 0xF,
@@ -396,13 +417,17 @@ __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __
   using Frag = OmegaFrag<LR_PREC_BF16>;
   constexpr int BN = NW * 16 * WC;
   constexpr int GPT = 64 / NW;  // kernel entries per thread per step (8 or 16)
+#ifdef LR_B16_VALU_PER_MFMA
+  constexpr int kValuPerMfma = LR_B16_VALU_PER_MFMA;
+#else
   constexpr int kValuPerMfma = (9 * GPT / (8 * WC)) > 2 ? (9 * GPT / (8 * WC)) : 2;
+#endif
   static_assert(NW == 4 || NW == 8, "4 or 8 waves");
 
   __shared__ __align__(16) __bf16 tile[2][4 * kDenseRows * 8];  // [buf][k-group][row][8]
 
   const int tid = threadIdx.x;
-  const int w = tid >> 6;
+  const int w = wave_uniform(tid >> 6);
   const int lane = tid & 63;
   const int grow = (w & 1) * 64 + lane;  // generation: row of the tile
   const int gg = wave_uniform(w >> 1);   // generation: j = GPT gg .. GPT gg + GPT - 1 of the step
@@ -436,10 +461,24 @@ __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __
     // kPointPad zero rows past n (steps up to nst + 2 are read), and kernel
     // values there meet zero Omega rows
     using Pts = float[ND];
+    const __amdgpu_buffer_rsrc_t pview = buffer_view(pts, (uint32_t)((n + kPointPad) * PD * sizeof(float)));
+    const uint32_t poff = (uint32_t)((GPT * gg + (fl & (GPT - 1))) * PD * sizeof(float));
     auto load_pts = [&](int64_t step, Pts& p) {
-      const int64_t j = step * kDenseStep + GPT * gg + (fl & (GPT - 1));
-#pragma unroll
-      for (int t = 0; t < ND; ++t) p[t] = pts[j * PD + t];
+      const int soff = (int)(step * (kDenseStep * PD * sizeof(float)));
+      // (the builtins return plain vector_size vectors: copy them out bytewise)
+      if constexpr (ND == 1) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b32(pview, poff, soff, 0);
+        static_assert(sizeof(v) >= 4, "load width");
+        __builtin_memcpy(&p[0], &v, 4);
+      } else if constexpr (ND == 2) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(pview, poff, soff, 0);
+        static_assert(sizeof(v) >= 8, "load width");
+        __builtin_memcpy(&p[0], &v, 8);
+      } else {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b96(pview, poff, soff, 0);
+        static_assert(sizeof(v) >= 12, "load width");
+        __builtin_memcpy(&p[0], &v, 12);
+      }
     };
     __bf16 gen[GPT];
     auto generate = [&](const Pts& p) {
@@ -462,27 +501,32 @@ __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __
         for (int e = 0; e < 8; ++e) dst[e] = gen[8 * u + e];
       }
     };
-    // this wave's fragments: wave-uniform base plus 32-bit lane offsets
-    const uint4* fbase = frag + (int64_t)(colw / 16) * nst * 64;
-    uint32_t foff[WC];
+    // this wave's fragments: one buffer view per 16-column group (nst steps
+    // of 1 KB; the prefetch past the last step reads zeros), lane offset
+    // 16 lane bytes
+    __amdgpu_buffer_rsrc_t fview[WC];
 #pragma unroll
-    for (int c = 0; c < WC; ++c) foff[c] = (uint32_t)((int64_t)c * nst * 64 + lane);
+    for (int c = 0; c < WC; ++c)
+      fview[c] = buffer_view(frag + (int64_t)(colw / 16 + c) * nst * 64, (uint32_t)(nst * 64 * sizeof(uint4)));
+    const uint32_t foff = (uint32_t)lane * sizeof(uint4);
     auto load_b = [&](int64_t s, Frag (&dst)[WC]) {
-      const uint4* p = fbase + s * 64;
+      const int soff = (int)(s * (64 * sizeof(uint4)));
 #pragma unroll
       for (int c = 0; c < WC; ++c) {
-        const uint4 raw = p[foff[c]];
+        const auto raw = __builtin_amdgcn_raw_buffer_load_b128(fview[c], foff, soff, 0);
+        static_assert(sizeof(raw) == 16, "load width");
         __builtin_memcpy(&dst[c].v[0], &raw, 16);
       }
     };
-    // Step s: b holds Omega of step s, bl receives Omega of step s + 1, pg
-    // holds the points of step s + 1, pl receives those of step s + 3. The
+    // Step s: b holds Omega of step s, bl receives Omega of step
+    // s + kB16Ahead, pg holds the points of step s + 1, pl receives those of
+    // step s + 3. The
     // loads, the evaluation and the tile store are unconditional (the last
     // steps read the zero padding past the data and their tiles are never
     // used), so no branch hides from the compiler how many loads are in flight.
     auto step_body = [&](int64_t s, Frag (&b)[WC], Frag (&bl)[WC], const Pts& pg, Pts& pl) {
       const int cur = (int)(s & 1);
-      load_b(s + 1, bl);
+      load_b(s + kB16Ahead, bl);
       load_pts(s + 3, pl);
       Frag a[8];
 #pragma unroll
@@ -497,34 +541,58 @@ __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __
 #pragma unroll
         for (int c = 0; c < WC; ++c) mfma_step<LR_PREC_BF16>(acc[f][c], a[f], b[c]);
       store_gen(cur ^ 1);
+      // issue order: the tile reads and operand loads, then every
+      // matrix-core operation followed by a few vector instructions of the
+      // evaluation, so the vector work runs while the matrix cores are busy
+      if constexpr (kB16Interleave) {
+        __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x020, WC + 1, 0);
+        static_for<0, 8 * WC>([&](auto ii) {
+          constexpr int i = decltype(ii)::value;
+          if constexpr (i % WC == 0 && i / WC < 6) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x002, kValuPerMfma, 0);
+        });
+        __builtin_amdgcn_sched_group_barrier(0x200, GPT / 8, 0);
+      }
       __syncthreads();
       // keep each step's instructions inside the step, so loads issued at its
       // start are not sunk towards their uses one or two steps later
       __builtin_amdgcn_sched_barrier(0);
     };
 
-    // Omega in 2 alternating register sets (one step ahead), points in 3
-    // rotating sets (two steps ahead): six steps per loop trip.
-    Frag bs[2][WC];
+    // Omega in kB16Ahead + 1 rotating register sets, points in 3 rotating
+    // sets (two steps ahead): six steps per loop trip.
+    constexpr int NB = kB16Ahead + 1;
+    static_assert(6 % NB == 0, "register sets rotate within a loop trip");
+    Frag bs[NB][WC];
     Pts ps[3];
+    // prologue: the loads in the order the steps issue them ([Omega, points]
+    // per step), so the waits of the first loop step match the later ones
     load_pts(0, ps[0]);
+    constexpr int kPro = kB16Ahead > 2 ? kB16Ahead : 2;
+    static_for<0, kPro>([&](auto kk) {
+      constexpr int k = decltype(kk)::value;
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (k < kB16Ahead) load_b(k, bs[k]);
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (k < 2) load_pts(k + 1, ps[k + 1]);
+    });
+    __builtin_amdgcn_sched_barrier(0);
     generate(ps[0]);
     store_gen(0);
-    load_b(0, bs[0]);
-    load_pts(1, ps[1]);
-    load_pts(2, ps[2]);
     __syncthreads();
 
     int64_t s = 0;
     for (; s + 6 <= nst; s += 6) {
       static_for<0, 6>([&](auto kk) {
         constexpr int k = decltype(kk)::value;
-        step_body(s + k, bs[k % 2], bs[(k + 1) % 2], ps[(k + 1) % 3], ps[k % 3]);
+        step_body(s + k, bs[k % NB], bs[(k + kB16Ahead) % NB], ps[(k + 1) % 3], ps[k % 3]);
       });
     }
     static_for<0, 5>([&](auto kk) {
       constexpr int k = decltype(kk)::value;
-      if (s + k < nst) step_body(s + k, bs[k % 2], bs[(k + 1) % 2], ps[(k + 1) % 3], ps[k % 3]);
+      if (s + k < nst) step_body(s + k, bs[k % NB], bs[(k + kB16Ahead) % NB], ps[(k + 1) % 3], ps[k % 3]);
     });
 
 #pragma unroll
@@ -560,10 +628,11 @@ int64_t omega_frag_cols(int d) {
   return d <= kB16Waves * 16 ? kB16Waves * 16 : (d <= 2 * kB16Waves * 16 ? 2 * kB16Waves * 16 : (d + bn - 1) / bn * bn);
 }
 
-// plus one zero step of padding, read by the last step's (unused) prefetch
+// plus kB16Ahead zero steps of padding, read by the last steps' (unused)
+// prefetches
 size_t omega_frag_bytes(int64_t n, int d) {
   const int64_t nst = (n + kDenseStep - 1) / kDenseStep;
-  return ((size_t)(omega_frag_cols(d) / 16) * nst + 1) * 64 * 16;
+  return ((size_t)(omega_frag_cols(d) / 16) * nst + kB16Ahead) * 64 * 16;
 }
 
 template <int KERNEL, int PD, int ND, int WC, bool DERIV>
@@ -574,6 +643,8 @@ static hipError_t launch_bf16_impl(hipStream_t st, const void* pts, const uint4*
   const int nrb = (int)((n + kDenseRows - 1) / kDenseRows);
   const int ncb = (d + BN - 1) / BN;
   const int64_t nst = (n + kDenseStep - 1) / kDenseStep;
+  // buffer views take 31-bit byte extents: 1 KB per step of a column group
+  if (n > kBf16MaxRows) return hipErrorInvalidValue;
   int64_t blocks = (int64_t)nrb * ncb;
   if (blocks > num_cu) blocks = num_cu;
   hipLaunchKernelGGL((sketch_bf16_kernel<NW, KERNEL, PD, ND, WC, DERIV>), dim3((unsigned)blocks), dim3(NW * 64), 0,
@@ -597,7 +668,7 @@ static hipError_t launch_bf16_wc(hipStream_t st, const void* pts, const uint4* f
 
 hipError_t launch_omega_frag(hipStream_t st, const void* omt, int64_t ld, int64_t n, int d, void* frag) {
   const int64_t nst = (n + kDenseStep - 1) / kDenseStep;
-  const int64_t total = (omega_frag_cols(d) / 16 * nst + 1) * 64;  // the last step is the zero pad
+  const int64_t total = (omega_frag_cols(d) / 16 * nst + kB16Ahead) * 64;  // the last steps are the zero pad
   const int threads = 256;
   hipLaunchKernelGGL(omega_frag_kernel, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0, st,
                      (const uint16_t*)omt, ld, n, d, nst, total, (uint4*)frag);

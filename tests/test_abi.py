@@ -85,6 +85,8 @@ def test_sketch_validation():
     assert _sketch(om=_srht(512, 64)) == L.LR_ERR_SHAPE  # omega->n != n
     assert _sketch(om=_gauss(1000, 64, 1001), n=1000) == L.LR_ERR_SHAPE  # ld % 8
     assert _sketch(om=_gauss(1000, 64, 992), n=1000) == L.LR_ERR_SHAPE  # ld < n
+    big = (1 << 25) + 8
+    assert _sketch(om=_gauss(big, 64, big), n=big, prec=L.LR_PREC_BF16) == L.LR_ERR_UNSUPPORTED  # bf16 n > 2^25
     assert _sketch(y=None, yp=None) == L.LR_ERR_ARG
     assert _sketch(ws_bytes=16) == L.LR_ERR_WORKSPACE
 
