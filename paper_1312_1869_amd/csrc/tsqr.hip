@@ -16,6 +16,8 @@
 // B -= V (T' (V^T B)) per outer panel on the matrix cores.
 #include <vector>
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -116,6 +118,27 @@ __device__ __forceinline__ RowMap make_rowmap(int m, int p0, int tree_d) {
     rm.nact = m - p0;
   }
   return rm;
+}
+
+// Row r of the compact-WY T of one panel: T[r][c] = 0 for c < r, tau_r on the
+// diagonal, -tau_c sum_{q=r}^{c-1} T[r][q] y_c[q] right of it, where
+// y_c[q] = v_q^T v_c. Register array indices are compile-time constants.
+template <typename T, int NB>
+__device__ __forceinline__ void row_t_build(T (&row)[NB], int r, int nbw, const T* s_tau, const T* s_y) {
+  static_for<0, NB>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    if (c < nbw) {
+      if (c == r) {
+        row[c] = s_tau[c];
+      } else if (c > r) {
+        T acc = 0;
+#pragma unroll
+        for (int q = 0; q < c; ++q)
+          if (q >= r) acc += row[q] * s_y[c * NB + q];
+        row[c] = -s_tau[c] * acc;
+      }
+    }
+  });
 }
 
 // Factor columns [p0, p0 + nbw) of every matrix in the batch.
@@ -229,22 +252,22 @@ __global__ __launch_bounds__(TPB) void panel_factor_kernel(T* __restrict__ A, in
         if (c < nbw) M[roff + c] = a[k][c];
     }
   }
-  // T (upper triangular, LDS): T[c][c] = tau_c, T[0:c, c] = -tau_c T[0:c, 0:c] y_c,
-  // column by column, the entries of a column in parallel (thread r < c)
-  if (t < NB * NB) s_t[t] = 0;
+  // T (upper triangular): T[c][c] = tau_c, T[0:c, c] = -tau_c T[0:c, 0:c] y_c.
+  // Row r of T depends only on row r (T[r][c] = -tau_c sum_{q=r}^{c-1}
+  // T[r][q] y_c[q]), so thread r < nbw builds its row left to right in
+  // registers, with no barrier.
+  for (int i = t; i < NB * NB; i += TPB) s_t[i] = 0;
   __syncthreads();
-  for (int c = 0; c < nbw; ++c) {
-    const T tc = s_tau[c];
-    if (t < c) {
-      T s = 0;
-      for (int q = t; q < c; ++q) s += s_t[t * NB + q] * s_y[c * NB + q];
-      s_t[t * NB + c] = -tc * s;
-    } else if (t == c) {
-      s_t[c * NB + c] = tc;
-    }
-    __syncthreads();
+  if (t < nbw) {
+    T row[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) row[c] = 0;
+    row_t_build<T, NB>(row, t, nbw, s_tau, s_y);
+#pragma unroll
+    for (int c = 0; c < NB; ++c) s_t[t * NB + c] = row[c];
   }
-  if (t < NB * NB) tmat[(int64_t)b * t_bstride + t] = s_t[t];
+  __syncthreads();
+  for (int i = t; i < NB * NB; i += TPB) tmat[(int64_t)b * t_bstride + i] = s_t[i];
   if (t < nbw) tau_all[(int64_t)b * tau_bstride + p0 + t] = s_tau[t];
 }
 
@@ -910,9 +933,29 @@ static hipError_t launch_panel_factor_rn(hipStream_t st, T* A, int64_t bstride, 
   return hipGetLastError();
 }
 
+template <typename T, int NB, int TPB>
+static hipError_t launch_panel_factor_small(hipStream_t st, T* A, int64_t bstride, const QrShape& s, int p0, int nbw,
+                                            T* tau, T* tm) {
+  hipLaunchKernelGGL((panel_factor_kernel<T, 1, NB, TPB>), dim3(s.nbatch), dim3(TPB), 0, st, A, bstride, s.m_full,
+                     s.m_last, s.nbatch, s.d, p0, nbw, s.tree_d, tau, (int64_t)s.d, tm, (int64_t)s.npanels * NB * NB);
+  return hipGetLastError();
+}
+
 template <typename T, int NB>
 static hipError_t launch_panel_factor_nb(hipStream_t st, int rpt, T* A, int64_t bstride, const QrShape& s, int p0,
                                          int nbw, T* tau, T* tm) {
+  // Tree panels touch NB top rows and p0 + NB bottom rows (see RowMap): the
+  // smallest workgroup holding one of them per thread does the panel, so the
+  // early panels pay for fewer waves at every barrier.
+  if constexpr (std::is_same<T, double>::value) {
+    if (s.tree_d > 0) {
+      const int nact = (NB < s.tree_d - p0 ? NB : s.tree_d - p0) + (p0 + NB < s.tree_d ? p0 + NB : s.tree_d);
+      if (nact <= 64) return launch_panel_factor_small<T, NB, 64>(st, A, bstride, s, p0, nbw, tau, tm);
+      if (nact <= 128) return launch_panel_factor_small<T, NB, 128>(st, A, bstride, s, p0, nbw, tau, tm);
+      if (nact <= 256) return launch_panel_factor_small<T, NB, 256>(st, A, bstride, s, p0, nbw, tau, tm);
+      if (nact <= kFactorThreads) rpt = 1;
+    }
+  }
   switch (rpt) {
     case 1: return launch_panel_factor_rn<T, 1, NB>(st, A, bstride, s, p0, nbw, tau, tm);
     case 2: return launch_panel_factor_rn<T, 2, NB>(st, A, bstride, s, p0, nbw, tau, tm);
