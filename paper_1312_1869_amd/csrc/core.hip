@@ -50,6 +50,7 @@ __device__ __forceinline__ void argmax_dpp(double& a, int& i) {
   }
 }
 
+template <int NWV>
 __device__ __forceinline__ int block_argmax_db(double v, int idx, double* redv, int* redi, int& parity) {
   double a = v;
   int i = idx;
@@ -69,8 +70,8 @@ __device__ __forceinline__ int block_argmax_db(double v, int idx, double* redv, 
     }
   }
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double* bv = redv + parity * kCoreWaves;
-  int* bi = redi + parity * kCoreWaves;
+  double* bv = redv + parity * NWV;
+  int* bi = redi + parity * NWV;
   parity ^= 1;
   if (lane == 0) {
     bv[w] = a;
@@ -79,7 +80,7 @@ __device__ __forceinline__ int block_argmax_db(double v, int idx, double* redv, 
   __syncthreads();
   double ba = -1.0;
   int best = 0x7fffffff;
-  for (int k = 0; k < kCoreWaves; ++k) {
+  for (int k = 0; k < NWV; ++k) {
     if (bv[k] > ba || (bv[k] == ba && bi[k] < best)) {
       ba = bv[k];
       best = bi[k];
@@ -88,10 +89,13 @@ __device__ __forceinline__ int block_argmax_db(double v, int idx, double* redv, 
   return best;
 }
 
-__global__ __launch_bounds__(kCoreThreads) void lu_panel_kernel(int d, double* A, int k0, int32_t* piv,
-                                                                int32_t* info, double* logdet) {
-  __shared__ double redv[2 * kCoreWaves];
-  __shared__ int redi[2 * kCoreWaves];
+// TPB >= d - k0 threads: one panel row each.
+template <int TPB>
+__global__ __launch_bounds__(TPB) void lu_panel_kernel(int d, double* A, int k0, int32_t* piv, int32_t* info,
+                                                       double* logdet) {
+  constexpr int NWV = TPB / 64;
+  __shared__ double redv[2 * NWV];
+  __shared__ int redi[2 * NWV];
   __shared__ double prow[2][kPanel];
   __shared__ double krow[2][kPanel];
   if (*info != 0) return;
@@ -111,7 +115,7 @@ __global__ __launch_bounds__(kCoreThreads) void lu_panel_kernel(int d, double* A
     const int k = k0 + c;
     // candidate magnitude on rows >= k (NaN never wins)
     const double mag = (have && r >= k) ? fabs(a[c]) : -1.0;
-    int p = block_argmax_db(mag == mag ? mag : -1.0, have && r >= k ? r : 0x7fffffff, redv, redi, par);
+    int p = block_argmax_db<NWV>(mag == mag ? mag : -1.0, have && r >= k ? r : 0x7fffffff, redv, redi, par);
     if (p < k || p >= d) p = k;
     const int buf = c & 1;
     if (r == p) {
@@ -479,7 +483,20 @@ hipError_t launch_core(hipStream_t st, int64_t n, int d, const double* F, const 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   for (int k0 = 0; k0 < d; k0 += kPanel) {
-    hipLaunchKernelGGL(lu_panel_kernel, dim3(1), dim3(kCoreThreads), 0, st, d, Flu, k0, piv, info, logdet);
+    // the smallest workgroup with a thread for each of the d - k0 panel rows
+    const int rows = d - k0;
+    if (rows <= 64) {
+      hipLaunchKernelGGL(lu_panel_kernel<64>, dim3(1), dim3(64), 0, st, d, Flu, k0, piv, info, logdet);
+    } else if (rows <= 128) {
+      hipLaunchKernelGGL(lu_panel_kernel<128>, dim3(1), dim3(128), 0, st, d, Flu, k0, piv, info, logdet);
+    } else if (rows <= 256) {
+      hipLaunchKernelGGL(lu_panel_kernel<256>, dim3(1), dim3(256), 0, st, d, Flu, k0, piv, info, logdet);
+    } else if (rows <= 512) {
+      hipLaunchKernelGGL(lu_panel_kernel<512>, dim3(1), dim3(512), 0, st, d, Flu, k0, piv, info, logdet);
+    } else {
+      hipLaunchKernelGGL(lu_panel_kernel<kCoreThreads>, dim3(1), dim3(kCoreThreads), 0, st, d, Flu, k0, piv, info,
+                         logdet);
+    }
     const int kend = min(k0 + kPanel, d);
     const int nblk = (k0 + kLuCols - 1) / kLuCols + (d - kend + kLuCols - 1) / kLuCols;
     if (nblk > 0) hipLaunchKernelGGL(lu_update_kernel, dim3(nblk), dim3(256), 0, st, d, Flu, k0, piv, info);
