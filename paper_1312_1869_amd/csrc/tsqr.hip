@@ -162,13 +162,27 @@ __global__ __launch_bounds__(TPB) void panel_factor_kernel(T* __restrict__ A, in
   const int rows = rm.nact;
   const int t = threadIdx.x;
 
+  // a full-width panel whose rows start on 16-byte boundaries moves as
+  // 16-byte vectors (NB * sizeof(T) / 16 per row) instead of NB scalars
+  constexpr int kVecs = NB * (int)sizeof(T) / 16;
+  const bool vec = kVecs > 0 && nbw == NB && ((int64_t)ld * sizeof(T)) % 16 == 0 &&
+                   (reinterpret_cast<uintptr_t>(M + p0) % 16) == 0;
   T a[RPT][NB];
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     const int lr = t + k * TPB;
     const int64_t roff = (lr < rows) ? (int64_t)rm.row(lr) * ld + p0 : 0;
+    if (vec) {
 #pragma unroll
-    for (int c = 0; c < NB; ++c) a[k][c] = (lr < rows && c < nbw) ? M[roff + c] : (T)0;
+      for (int q = 0; q < kVecs; ++q) {
+        uint4 v = {0u, 0u, 0u, 0u};
+        if (lr < rows) v = reinterpret_cast<const uint4*>(M + roff)[q];
+        __builtin_memcpy(&a[k][q * (16 / sizeof(T))], &v, 16);
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) a[k][c] = (lr < rows && c < nbw) ? M[roff + c] : (T)0;
+    }
   }
 
   // Expanded at compile time so every register-array index is a constant.
@@ -247,9 +261,18 @@ __global__ __launch_bounds__(TPB) void panel_factor_kernel(T* __restrict__ A, in
     const int lr = t + k * TPB;
     if (lr < rows) {
       const int64_t roff = (int64_t)rm.row(lr) * ld + p0;
+      if (vec) {
 #pragma unroll
-      for (int c = 0; c < NB; ++c)
-        if (c < nbw) M[roff + c] = a[k][c];
+        for (int q = 0; q < kVecs; ++q) {
+          uint4 v;
+          __builtin_memcpy(&v, &a[k][q * (16 / sizeof(T))], 16);
+          reinterpret_cast<uint4*>(M + roff)[q] = v;
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+          if (c < nbw) M[roff + c] = a[k][c];
+      }
     }
   }
   // T (upper triangular): T[c][c] = tau_c, T[0:c, c] = -tau_c T[0:c, 0:c] y_c.
