@@ -234,14 +234,15 @@ __global__ __launch_bounds__(256) void lu_update_kernel(int d, double* A, int k0
 }
 
 // ---- blocked Cholesky of the lower triangle (panels of kPanel columns).
-__global__ __launch_bounds__(kCoreThreads) void chol_panel_kernel(int d, double* L, int k0, int32_t* info,
-                                                                  double* logdet) {
+// TPB >= d - k0 - kPanel threads (one row below the diagonal block each), TPB >= 64.
+template <int TPB>
+__global__ __launch_bounds__(TPB) void chol_panel_kernel(int d, double* L, int k0, int32_t* info, double* logdet) {
   __shared__ double Lkk[kPanel][kPanel + 1];
   __shared__ int bad;
   if (*info != 0) return;
   const int t = threadIdx.x;
   const int nb = min(kPanel, d - k0);
-  for (int e = t; e < kPanel * kPanel; e += kCoreThreads) {
+  for (int e = t; e < kPanel * kPanel; e += TPB) {
     const int i = e / kPanel, j = e % kPanel;
     Lkk[i][j] = (i < nb && j < nb && j <= i) ? L[(int64_t)(k0 + i) * d + k0 + j] : 0.0;
   }
@@ -276,11 +277,11 @@ __global__ __launch_bounds__(kCoreThreads) void chol_panel_kernel(int d, double*
     }
     return;
   }
-  for (int e = t; e < kPanel * kPanel; e += kCoreThreads) {
+  for (int e = t; e < kPanel * kPanel; e += TPB) {
     const int i = e / kPanel, j = e % kPanel;
     if (i < nb && j < nb && j <= i) L[(int64_t)(k0 + i) * d + k0 + j] = Lkk[i][j];
   }
-  // rows below: L[i, panel] = A[i, panel] Lkk^{-T} (one row per thread: d <= kCoreThreads)
+  // rows below: L[i, panel] = A[i, panel] Lkk^{-T} (one row per thread: d - k0 - nb <= TPB)
   const int i = k0 + nb + t;
   if (i < d) {
     double y[kPanel];
@@ -507,7 +508,19 @@ hipError_t launch_core(hipStream_t st, int64_t n, int d, const double* F, const 
   hipLaunchKernelGGL(shift_lower_kernel, dim3(ddb), dim3(256), 0, st, d, sigma2, nu, C, L, info);
   hipLaunchKernelGGL(sym_kernel, dim3(ddb), dim3(256), 0, st, d, C, info);
   for (int k0 = 0; k0 < d; k0 += kPanel) {
-    hipLaunchKernelGGL(chol_panel_kernel, dim3(1), dim3(kCoreThreads), 0, st, d, L, k0, info, logdet);
+    // the smallest workgroup with a thread for each row below the diagonal block
+    const int below = d - min(k0 + kPanel, d);
+    if (below <= 64) {
+      hipLaunchKernelGGL(chol_panel_kernel<64>, dim3(1), dim3(64), 0, st, d, L, k0, info, logdet);
+    } else if (below <= 128) {
+      hipLaunchKernelGGL(chol_panel_kernel<128>, dim3(1), dim3(128), 0, st, d, L, k0, info, logdet);
+    } else if (below <= 256) {
+      hipLaunchKernelGGL(chol_panel_kernel<256>, dim3(1), dim3(256), 0, st, d, L, k0, info, logdet);
+    } else if (below <= 512) {
+      hipLaunchKernelGGL(chol_panel_kernel<512>, dim3(1), dim3(512), 0, st, d, L, k0, info, logdet);
+    } else {
+      hipLaunchKernelGGL(chol_panel_kernel<kCoreThreads>, dim3(1), dim3(kCoreThreads), 0, st, d, L, k0, info, logdet);
+    }
     const int base = min(k0 + kPanel, d);
     const int nt = (d - base + 63) / 64;
     if (nt > 0) hipLaunchKernelGGL(chol_update_kernel, dim3(nt * (nt + 1) / 2), dim3(256), 0, st, d, L, k0, info);
