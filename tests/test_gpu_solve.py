@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import grad as og, lowrank as olr
+from oracle import grad as og, lowrank as olr, sketch as osk
 
 from gpu_common import api, device, hyper, note, omega_pair, rel_max, to_dev, torch
 
@@ -69,6 +69,26 @@ def test_gauss_fp64_small_with_shift(nu):
     el = abs(sol.logdet.item() - ref["logdet"]) / abs(ref["logdet"])
     note(f"  X rel {ex:.2e} logdet rel {el:.2e}")
     assert ex <= 1e-10 and el <= 1e-10
+
+
+def test_gauss_fp64_largest_d():
+    """d = 1024, the largest rank the boundary takes: 1024-thread LU and
+    Cholesky panels and tree panels with several rows per thread. Reference:
+    the oracle's sketch and Woodbury solve around the unique positive-diagonal
+    QR of Y (LAPACK's, sign-fixed; the oracle's own column-by-column QR needs
+    tens of seconds at this size)."""
+    dev = device()
+    w = W.small(W.WORKLOADS["C3"], 2048, d=1024, leaf_rows=1024, m=2).replace(ell=0.1, sigma2=1e-1)
+    x, A, om_np, _, Y, Q, R, sol = _forward(w.replace(prec="f64"), "f64", dev)
+    y = osk.sketch(x, w.kernel, w.ell, w.s, om_np)
+    q, r = np.linalg.qr(y)
+    sg = np.where(np.diag(r) < 0, -1.0, 1.0)
+    ref = olr.solve(q * sg[None, :], r * sg[:, None], om_np, w.sigma2, A)
+    ex = rel_max(sol.X.cpu().numpy(), ref["X"])
+    el = abs(sol.logdet.item() - ref["logdet"]) / abs(ref["logdet"])
+    note(f"  X rel {ex:.2e} logdet rel {el:.2e}")
+    assert int(sol.info.item()) == 0
+    assert ex <= 1e-9 and el <= 1e-10
 
 
 def test_srht_fp32_path_error_vs_fp64_oracle():

@@ -101,3 +101,35 @@ def test_tsqr_kernel_sketch_full_size_properties(name, prec):
     assert np.all(np.tril(r, -1) == 0.0) and np.all(np.diag(r) >= 0)
     assert orth <= 50 * math.sqrt(w.n) * u
     assert back <= 50 * math.sqrt(w.n) * u
+
+
+def _unique_qr(y):
+    """QR of a full-rank y with R's diagonal made positive: then Q and R are
+    unique, so any correct algorithm (here LAPACK's) gives the same factors."""
+    q, r = np.linalg.qr(y)
+    sg = np.where(np.diag(r) < 0, -1.0, 1.0)
+    return q * sg[None, :], r * sg[:, None]
+
+
+@pytest.mark.parametrize("prec,n,d,leaf", [("f64", 4096, 1024, 2048), ("f32", 6144, 1024, 1536)])
+def test_tsqr_largest_d_matches_unique_qr(prec, n, d, leaf):
+    """d = 1024, the largest rank the boundary takes (tree panels with several
+    rows per thread). The pin is the unique positive-diagonal QR."""
+    dev = device()
+    y = _gauss_y(n, d, 11 * n + d)
+    if prec == "f32":
+        y = y.astype(np.float32)
+    Y, Q, R = _run(y, leaf, prec, dev)
+    qo, ro = _unique_qr(np.asarray(y, dtype=np.float64))
+    orth, back, r = _props(Y, Q, R)
+    u = U64 if prec == "f64" else U32
+    err_r = np.abs(r - ro).max() / np.abs(ro).max()
+    err_q = np.abs(Q.double().cpu().numpy() - qo).max()
+    note(f"  orth {orth:.2e} back {back:.2e} R err {err_r:.2e} Q err {err_q:.2e}")
+    assert np.all(np.tril(r, -1) == 0.0) and np.all(np.diag(r) >= 0)
+    if prec == "f64":
+        assert orth <= 50 * math.sqrt(n) * u and back <= 50 * math.sqrt(n) * u
+        assert err_r <= 1e-12 and err_q <= 1e-11
+    else:
+        tol = 20 * math.sqrt(n) * u
+        assert orth <= tol and back <= tol and err_r <= 4 * tol and err_q <= 4 * tol
