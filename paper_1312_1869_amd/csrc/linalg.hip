@@ -189,7 +189,8 @@ __global__ __launch_bounds__(256) void gemm_tn_xt_kernel(int64_t n, int64_t chun
         acc64[f][t][q] = 0.0;
       }
   struct Step {
-    float x[2][8];
+    float x[2][8];   // float Omega
+    uint4 xr[2];     // bf16 Omega, 8 rows of a column as loaded
     float y[8][4];
   };
   // rows r0 + 8 fg + e; FULL: all 32 rows < rend
@@ -203,17 +204,23 @@ __global__ __launch_bounds__(256) void gemm_tn_xt_kernel(int64_t n, int64_t chun
       if (!full && rr >= rend) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) st.x[f][e] = 0.0f;
+        st.xr[f] = uint4{0u, 0u, 0u, 0u};
         continue;
       }
       if constexpr (XDT == 2) {
         const uint16_t* src = static_cast<const uint16_t*>(xptr) + col * xld + rr;
         uint4 raw = *reinterpret_cast<const uint4*>(src);
-        const uint32_t wv[4] = {raw.x, raw.y, raw.z, raw.w};
+        if (!full) {  // rows past rend: element 2q is the low half of word q
+          uint32_t wv[4] = {raw.x, raw.y, raw.z, raw.w};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          st.x[f][2 * q] = __uint_as_float(wv[q] << 16);
-          st.x[f][2 * q + 1] = __uint_as_float(wv[q] & 0xffff0000u);
+          for (int q = 0; q < 4; ++q) {
+            if (rr + 2 * q >= rend) wv[q] &= 0xffff0000u;
+            if (rr + 2 * q + 1 >= rend) wv[q] &= 0x0000ffffu;
+          }
+          raw = uint4{wv[0], wv[1], wv[2], wv[3]};
         }
+        st.xr[f] = raw;
+        continue;
       } else {
         const float* src = static_cast<const float*>(xptr) + col * xld + rr;
         const float4 a = *reinterpret_cast<const float4*>(src);
@@ -239,13 +246,43 @@ __global__ __launch_bounds__(256) void gemm_tn_xt_kernel(int64_t n, int64_t chun
     }
   };
   auto mma_step = [&](const Step& st) {
+    if constexpr (XDT == 2) {
+      // bf16 Omega: each float of Y is the exact sum of three bf16 terms
+      // (8 + 8 + 8 significand bits), and a bf16 x bf16 product is exact in
+      // float, so three bf16 matrix-core products per tile give the float
+      // product with float accumulation, at the bf16 rate
+      bf16x8_t a[2];
 #pragma unroll
-    for (int e = 0; e < 8; ++e)
+      for (int f = 0; f < 2; ++f) __builtin_memcpy(&a[f], &st.xr[f], 16);
 #pragma unroll
-      for (int f = 0; f < 2; ++f)
+      for (int t = 0; t < 4; ++t) {
+        bf16x8_t hi, mid, lo;
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-          acc[f][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(st.x[f][e], st.y[e][t], acc[f][t], 0, 0, 0);
+        for (int e = 0; e < 8; ++e) {
+          const float v = st.y[e][t];
+          const __bf16 h = (__bf16)v;
+          const float r1 = v - (float)h;
+          const __bf16 m = (__bf16)r1;
+          hi[e] = h;
+          mid[e] = m;
+          lo[e] = (__bf16)(r1 - (float)m);
+        }
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+          acc[f][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[f], hi, acc[f][t], 0, 0, 0);
+          acc[f][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[f], mid, acc[f][t], 0, 0, 0);
+          acc[f][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[f], lo, acc[f][t], 0, 0, 0);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            acc[f][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(st.x[f][e], st.y[e][t], acc[f][t], 0, 0, 0);
+    }
   };
   auto flush = [&]() {
 #pragma unroll
