@@ -15,9 +15,16 @@ Phi = F^{-1} (so Y W^{-1} = Q Phi):
     d/dlog s      = 2 tr(Q^T G Q C)            (N is proportional to s^2)
     d/dlog sigma2 = sigma2 tr(G)
 
-with, for the log-likelihood, Q^T K_tilde^{-1} = S^{-1} Q^T, so
-G Q = 1/2 (alpha a^T - Q S^{-1}), Q^T G Q = 1/2 (a a^T - S^{-1}), a = Q^T alpha,
-tr K_tilde^{-1} = (n - d) / sigma2 + tr S^{-1}.
+The Q-basis projections of the solves use the Woodbury identity
+Q^T K_tilde^{-1} = S^{-1} Q^T (Q has orthonormal columns in the method): for
+the log-likelihood a = Q^T alpha is taken as S^{-1} Q^T y, so
+G Q = 1/2 (alpha a^T - Q S^{-1}), Q^T G Q = 1/2 (a a^T - S^{-1}),
+tr K_tilde^{-1} = (n - d) / sigma2 + tr S^{-1}; for the solve Q^T X = S^{-1}
+Q^T A and Q^T B = S^{-1} Q^T Abar. The solves alpha, X, B themselves are the
+forward's K_tilde^{-1} applied to y, A, Abar. Written this way the formulas
+take Q, the core factors and Y' as given and never rely on Q^T Q = I holding
+to more than the method's own arithmetic, so they can also be evaluated on
+factors computed elsewhere (a reduced-precision Q promoted to float64).
 
 ``*_dense`` functions evaluate the same derivatives from the plain definition
 with explicit n x n matrices (small n): dN = Y' W^{-1} Y^T + Y W^{-1} Y'^T -
@@ -37,7 +44,7 @@ from . import kernels, lowrank, qr, sketch
 
 
 def _phi(core: dict) -> np.ndarray:
-    d = core["F"].shape[0]
+    d = core["F"].shape[0] if "F" in core else core["C"].shape[0]
     return sla.lu_solve(core["lu"], np.eye(d), check_finite=False)
 
 
@@ -53,19 +60,22 @@ def _theta_terms(q, core, omega, yprime, gq, qgq, trace_g, sigma2, trace_scale):
     return grad, scale
 
 
-def grad_loglik(x, kind, ell, s, sigma2, omega, q, core, y, alpha, yprime=None, parts=False):
+def grad_loglik(x, kind, ell, s, sigma2, omega, q, core, y, yprime=None, parts=False):
     """Gradient of the approximate log-likelihood (nu = 0).
 
-    With ``parts`` also returns, per component, the sum of the magnitudes of the
-    terms it adds up (|T1| + |T2| for log ell; for log s and log sigma2 the terms
-    of their closed forms, alpha^T y, sigma2 alpha^T alpha, n, sigma2 tr K~^{-1}).
+    ``core`` holds the forward's factors (``lu`` of F, ``C``, ``L``). With
+    ``parts`` also returns, per component, the sum of the magnitudes of the
+    terms it adds up (|T1| + |T2| for log ell; for log s and log sigma2 the
+    terms of their closed forms, alpha^T y, sigma2 alpha^T alpha, n,
+    sigma2 tr K~^{-1}).
     """
     q = np.asarray(q, dtype=np.float64)
     n, d = q.shape
-    alpha = np.asarray(alpha, dtype=np.float64).reshape(-1)
+    y = np.asarray(y, dtype=np.float64).reshape(-1)
     if yprime is None:
         yprime = sketch.sketch(x, kind, ell, s, omega, deriv=True)
-    a = q.T @ alpha
+    alpha = lowrank.apply(q, core["L"], y.reshape(-1, 1), sigma2)[:, 0]
+    a = lowrank.s_solve(core["L"], q.T @ y)
     s_inv = lowrank.s_solve(core["L"], np.eye(d))
     gq = 0.5 * (np.outer(alpha, a) - q @ s_inv)
     qgq = 0.5 * (np.outer(a, a) - s_inv)
@@ -73,21 +83,24 @@ def grad_loglik(x, kind, ell, s, sigma2, omega, q, core, y, alpha, yprime=None, 
     aa = float(alpha @ alpha)
     trace_g = 0.5 * (aa - tr_kinv)
     g, scale = _theta_terms(q, core, omega, yprime, gq, qgq, trace_g, sigma2, 0.5 * (aa + tr_kinv))
-    ya = abs(float(np.asarray(y, dtype=np.float64).reshape(-1) @ alpha))
+    ya = abs(float(y @ alpha))
     scale[1] = ya + sigma2 * aa + n + sigma2 * tr_kinv
     return (g, scale) if parts else g
 
 
-def grad_solve(x, kind, ell, s, sigma2, omega, q, core, xsol, abar, yprime=None, parts=False):
-    """Gradient of <Abar, K_tilde^{-1} A> (nu = 0). Returns (dtheta, dA), or
-    (dtheta, dA, scale) with ``parts`` (scale as in grad_loglik)."""
+def grad_solve(x, kind, ell, s, sigma2, omega, q, core, a, abar, yprime=None, parts=False):
+    """Gradient of <Abar, K_tilde^{-1} A> (nu = 0) for the forward's right-hand
+    side A. Returns (dtheta, dA), or (dtheta, dA, scale) with ``parts`` (scale
+    as in grad_loglik)."""
     q = np.asarray(q, dtype=np.float64)
-    xsol = np.asarray(xsol, dtype=np.float64)
+    a = np.asarray(a, dtype=np.float64)
+    abar = np.asarray(abar, dtype=np.float64)
+    xsol = lowrank.apply(q, core["L"], a, sigma2)
     b = lowrank.apply(q, core["L"], abar, sigma2)
     if yprime is None:
         yprime = sketch.sketch(x, kind, ell, s, omega, deriv=True)
-    qx = q.T @ xsol
-    qb = q.T @ b
+    qx = lowrank.s_solve(core["L"], q.T @ a)
+    qb = lowrank.s_solve(core["L"], q.T @ abar)
     gq = -0.5 * (xsol @ qb.T + b @ qx.T)
     qgq = -0.5 * (qx @ qb.T + qb @ qx.T)
     trace_g = -float(np.sum(xsol * b))

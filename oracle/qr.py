@@ -3,8 +3,8 @@
 Sec. 3.3, Eq. (1)-(4): split the tall sketch into row blocks K_i, factor each
 K_i = Q_i R_i (Eq. 1), stack the R_i and factor pairs of them (Eq. 2), repeat
 until one R is left (Eq. 3); the orthogonal factor is the product of the
-block-diagonal factors of every level (Eq. 4). Any number of blocks is allowed
-("appropriately adjusting the block sizes"): pairs are formed left to right and
+block-diagonal factors of every level (Eq. 4). Sec. 3.3 lets the block sizes
+vary, so any number of leaves is allowed: pairs are formed left to right and
 an unpaired last block is carried to the next level unchanged. The last row
 block may be shorter than the others but must have at least d rows.
 

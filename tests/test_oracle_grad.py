@@ -20,7 +20,7 @@ def test_loglik_gradient_fd_and_dense(kind):
     yv = W.gp_targets(w, x)
     f = grad.forward(x, kind, w.ell, w.s, w.sigma2, om, yv.reshape(-1, 1), w.leaf_rows)
     alpha = f["X"][:, 0]
-    g = grad.grad_loglik(x, kind, w.ell, w.s, w.sigma2, om, f["Q"], f, yv, alpha)
+    g = grad.grad_loglik(x, kind, w.ell, w.s, w.sigma2, om, f["Q"], f, yv)
     gd, _ = grad.grad_loglik_dense(x, kind, w.ell, w.s, w.sigma2, om, yv)
     np.testing.assert_allclose(g, gd, rtol=1e-7)
     th = np.log([w.ell, w.s, w.sigma2])
@@ -40,7 +40,7 @@ def test_solve_vjp_gradient_fd_and_dense():
     a = rng.standard_normal((w.n, 3))
     abar = rng.standard_normal((w.n, 3))
     f = grad.forward(x, "se", w.ell, w.s, w.sigma2, om, a, w.leaf_rows)
-    g, b = grad.grad_solve(x, "se", w.ell, w.s, w.sigma2, om, f["Q"], f, f["X"], abar)
+    g, b = grad.grad_solve(x, "se", w.ell, w.s, w.sigma2, om, f["Q"], f, a, abar)
     gd, bd = grad.grad_solve_dense(x, "se", w.ell, w.s, w.sigma2, om, a, abar)
     np.testing.assert_allclose(g, gd, rtol=1e-7)
     np.testing.assert_allclose(b, bd, rtol=1e-8, atol=1e-8 * np.abs(bd).max())
