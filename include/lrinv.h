@@ -135,7 +135,9 @@ lr_status lr_tsqr(void *stream, int64_t n, int32_t d, int32_t leaf_rows, int32_t
  * X = K~^{-1} A and log|K~| from the sketch factors (see the header comment).
  *   Q, R        outputs of lr_tsqr for the same Omega and nu.
  *   A, X        device real n x m (X may not alias A); m = 0 computes only the
- *               factors and log-determinant.
+ *               factors and log-determinant. Z = Q^T A is summed in float64 from
+ *               exact products and X = A/sigma2 + Q (S^{-1} Z - Z/sigma2) is
+ *               formed in float64 and rounded once to "real".
  *   C           device double d x d: sym(F^{-1} R^T).
  *   L           device double d x d: lower Cholesky factor of S (upper part 0).
  *   Flu, piv    device double d x d LU factors of F (unit lower L and U packed,
@@ -161,10 +163,21 @@ lr_status lr_loglik(void *stream, int64_t n, int32_t prec, const void *y, const 
 
 /* ---------------------------------------------------------------- backward
  * Gradient with respect to theta = (log ell, log s, log sigma2), nu = 0 only.
- *   mode 0 (log-likelihood -1/2 y^T K~^{-1} y - 1/2 log|K~|): U = alpha = K~^{-1} y
- *          (device real n x 1, m must be 1), V unused, dA unused.
- *   mode 1 (solve, cotangent Abar of X = K~^{-1} A): U = X (n x m), V = Abar
- *          (n x m); dA (device real n x m, or NULL) receives K~^{-1} Abar.
+ * (Not in the paper: the adjoint of steps 1-3 above.) For a symmetric G, the
+ * derivative of the objective with respect to K~, d/dtheta = tr(G dK~/dtheta)
+ * with, for Phi = F^{-1} and Y' = (dK_f/dlog ell) Omega,
+ *   d/dlog ell    = 2 <G Q Phi, Y'> - <Phi^T (Q^T G Q) Phi, Omega^T Y'>,
+ *   d/dlog s      = 2 tr(Q^T G Q C),   d/dlog sigma2 = sigma2 tr G.
+ *   mode 0 (log-likelihood -1/2 y^T K~^{-1} y - 1/2 log|K~|): G = (alpha alpha^T
+ *          - K~^{-1})/2. A = y, the forward's right-hand side (device real
+ *          n x 1, m must be 1); V and dA unused.
+ *   mode 1 (solve, cotangent Abar of X = K~^{-1} A): G = -(X B^T + B X^T)/2 with
+ *          B = K~^{-1} Abar. A = the forward's right-hand side (device real
+ *          n x m), V = Abar (n x m); dA (device real n x m, or NULL) receives B.
+ *   The solves alpha, X and B are recomputed here from A (and Abar) in float64
+ *   (Q^T A summed in float64 from exact products, S^{-1} by the Cholesky
+ *   factor), and their Q-basis projections are taken as S^{-1} Q^T A, so the
+ *   result does not depend on how closely a float32 Q satisfies Q^T Q = I.
  *   Q, C, L, Flu, piv   forward factors from lr_tsqr / lr_lowrank_solve.
  *   Yprime  device real n x d (dK_f/dlog ell) Omega from lr_sketch, or NULL to
  *           recompute it here (K tiles are recomputed, never stored).
@@ -173,13 +186,14 @@ size_t lr_backward_workspace_bytes(int64_t n, int32_t D, int32_t d, int32_t m, i
 lr_status lr_backward(void *stream, int64_t n, int32_t D, const float *X, const lr_hyper *hyp,
                       const lr_omega *omega, int32_t prec, const void *Q, const double *C,
                       const double *L, const double *Flu, const int32_t *piv, double sigma2,
-                      int32_t mode, int32_t m, const void *U, const void *V, const void *Yprime,
+                      int32_t mode, int32_t m, const void *A, const void *V, const void *Yprime,
                       double *dtheta, void *dA, void *ws, size_t ws_bytes);
 
 /* Human-readable status name (static string). */
 const char *lr_status_string(int32_t status);
 
-/* ABI version: (major << 16) | minor. */
+/* ABI version: (major << 16) | minor. 2.0: lr_backward takes the forward's
+ * right-hand side A instead of its solution. */
 int32_t lr_version(void);
 
 #ifdef __cplusplus

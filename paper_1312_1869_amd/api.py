@@ -171,18 +171,23 @@ def loglik(y: torch.Tensor, alpha: torch.Tensor, logdet: torch.Tensor, info: tor
 
 
 def backward(X: torch.Tensor, hyper: Hyper, omega: Omega, prec: str, fac: SolveOut, Q: torch.Tensor, sigma2: float,
-             mode: int, U: torch.Tensor, V: torch.Tensor | None = None, Yprime: torch.Tensor | None = None,
+             mode: int, A: torch.Tensor, V: torch.Tensor | None = None, Yprime: torch.Tensor | None = None,
              want_dA: bool = False):
+    """Gradient in (log ell, log s, log sigma2). ``A`` is the forward's
+    right-hand side (y for mode 0), ``V`` the cotangent Abar (mode 1)."""
     n, D = X.shape
     dev = X.device
-    m = int(U.shape[1]) if U.dim() == 2 else 1
+    _check_real(A, prec, "A")
+    if V is not None:
+        _check_real(V, prec, "V")
+    m = int(A.shape[1]) if A.dim() == 2 else 1
     dtheta = torch.empty(3, dtype=torch.float64, device=dev)
     dA = torch.empty_like(V) if (want_dA and V is not None) else None
     lib = L.lib()
     ws = _Workspace(lib.lr_backward_workspace_bytes(n, D, omega.d, m, L.PRECS[prec]), dev)
     h, o = hyper.struct(), omega.struct()
     L.check(lib.lr_backward(_stream(dev), n, D, _p(X), ctypes.byref(h), ctypes.byref(o), L.PRECS[prec], _p(Q),
-                            _p(fac.C), _p(fac.L), _p(fac.Flu), _p(fac.piv), float(sigma2), int(mode), m, _p(U), _p(V),
+                            _p(fac.C), _p(fac.L), _p(fac.Flu), _p(fac.piv), float(sigma2), int(mode), m, _p(A), _p(V),
                             _p(Yprime), _p(dtheta), _p(dA), ws.ptr, ws.nbytes), "lr_backward")
     return dtheta, dA
 

@@ -41,10 +41,10 @@ class LowRankSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, theta, A, X, omega, cfg: Config):
         hyper, sigma2 = _hyper(theta, cfg.kernel)
-        fw = api.forward(X, hyper, omega, cfg.prec, sigma2, A.contiguous(), cfg.leaf_rows, nu=cfg.nu,
-                         want_yprime=cfg.fused)
+        Ac = A.contiguous()
+        fw = api.forward(X, hyper, omega, cfg.prec, sigma2, Ac, cfg.leaf_rows, nu=cfg.nu, want_yprime=cfg.fused)
         _check_info(fw.sol)
-        ctx.save_for_backward(X, fw.Q, fw.sol.X)
+        ctx.save_for_backward(X, fw.Q, Ac)
         ctx.fac = fw.sol
         ctx.yprime = fw.Yprime
         ctx.omega, ctx.cfg, ctx.hyper, ctx.sigma2 = omega, cfg, hyper, sigma2
@@ -53,11 +53,11 @@ class LowRankSolve(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gX):
-        X, Q, Xs = ctx.saved_tensors
+        X, Q, A = ctx.saved_tensors
         if ctx.cfg.nu != 0.0:
             raise NotImplementedError("the adjoint is implemented for nu = 0")
-        dtheta, dA = api.backward(X, ctx.hyper, ctx.omega, ctx.cfg.prec, ctx.fac, Q, ctx.sigma2, 1, Xs,
-                                  V=gX.contiguous().to(Xs.dtype), Yprime=ctx.yprime, want_dA=True)
+        dtheta, dA = api.backward(X, ctx.hyper, ctx.omega, ctx.cfg.prec, ctx.fac, Q, ctx.sigma2, 1, A,
+                                  V=gX.contiguous().to(A.dtype), Yprime=ctx.yprime, want_dA=True)
         return dtheta.to(ctx.theta_device, ctx.theta_dtype), dA, None, None, None
 
 
@@ -71,7 +71,7 @@ class LowRankLogLik(torch.autograd.Function):
         fw = api.forward(X, hyper, omega, cfg.prec, sigma2, yc, cfg.leaf_rows, nu=cfg.nu, want_yprime=cfg.fused)
         _check_info(fw.sol)
         ll = api.loglik(yc, fw.sol.X, fw.sol.logdet, fw.sol.info, cfg.prec)
-        ctx.save_for_backward(X, fw.Q, fw.sol.X)
+        ctx.save_for_backward(X, fw.Q, yc)
         ctx.fac = fw.sol
         ctx.yprime = fw.Yprime
         ctx.omega, ctx.cfg, ctx.hyper, ctx.sigma2 = omega, cfg, hyper, sigma2
@@ -80,9 +80,9 @@ class LowRankLogLik(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
-        X, Q, alpha = ctx.saved_tensors
+        X, Q, yc = ctx.saved_tensors
         if ctx.cfg.nu != 0.0:
             raise NotImplementedError("the adjoint is implemented for nu = 0")
-        dtheta, _ = api.backward(X, ctx.hyper, ctx.omega, ctx.cfg.prec, ctx.fac, Q, ctx.sigma2, 0, alpha,
+        dtheta, _ = api.backward(X, ctx.hyper, ctx.omega, ctx.cfg.prec, ctx.fac, Q, ctx.sigma2, 0, yc,
                                  Yprime=ctx.yprime)
         return (g.to(torch.float64) * dtheta).to(ctx.theta_device, ctx.theta_dtype), None, None, None, None

@@ -166,18 +166,21 @@ lr_status sketch_impl(hipStream_t st, int64_t n, int32_t D, const float* X, cons
 // ---------------------------------------------------------------- lowrank solve
 
 struct SolveWs {
-  size_t off_f, off_z, off_w, off_tn, total;
+  size_t off_f, off_z, off_w, off_wm, off_tn, total;
 };
 
 SolveWs solve_layout(int64_t n, int32_t d, int32_t m) {
   SolveWs w;
+  const size_t dm = (size_t)d * (m > 0 ? m : 1) * 8;
   size_t off = 0;
   w.off_f = off;
   off = al(off + (size_t)d * d * 8);
   w.off_z = off;
-  off = al(off + (size_t)d * (m > 0 ? m : 1) * 8);
+  off = al(off + dm);
   w.off_w = off;
-  off = al(off + (size_t)d * (m > 0 ? m : 1) * 8);
+  off = al(off + dm);
+  w.off_wm = off;
+  off = al(off + dm);
   w.off_tn = off;
   size_t tn = tn_workspace(n, d, d);
   if (m > 0) {
@@ -189,80 +192,95 @@ SolveWs solve_layout(int64_t n, int32_t d, int32_t m) {
   return w;
 }
 
-// X = K~^{-1} A given Q and the Cholesky factor (used by solve and backward).
+// Z = Q^T A (float64 sums of exact products), W = S^{-1} Z, Wmix = W - Z/sigma2
+// (d x m float64 each).
+lr_status project_solve(hipStream_t st, int64_t n, int32_t d, int32_t m, int32_t prec, const void* Q,
+                        const double* L, double sigma2, const int32_t* info, const void* A, double* Z, double* W,
+                        double* Wmix, void* tnws) {
+  LR_HIP(launch_gemm_tn(st, n, d, m, real_operand(Q, d, prec), real_operand(A, m, prec), 1.0, Z, tnws, true));
+  LR_HIP(launch_core_apply(st, d, m, L, Z, sigma2, info, W, Wmix));
+  return LR_OK;
+}
+
+// X = K~^{-1} A = A/sigma2 + Q Wmix given Q and the Cholesky factor, in float64
+// and rounded once to the working precision.
 lr_status woodbury_apply(hipStream_t st, int64_t n, int32_t d, int32_t m, int32_t prec, const void* Q,
                          const double* L, double sigma2, const int32_t* info, const void* A, void* X, double* Z,
-                         double* W, void* tnws) {
+                         double* W, double* Wmix, void* tnws) {
   if (m <= 0) return LR_OK;
-  const bool f64 = prec == LR_PREC_F64;
-  LR_HIP(launch_gemm_tn(st, n, d, m, real_operand(Q, d, prec), real_operand(A, m, prec), 1.0, Z, tnws, f64));
-  LR_HIP(launch_core_apply(st, d, m, L, Z, sigma2, info, W));
-  LR_HIP(launch_rowmix_info(st, n, d, m, Q, W, 1.0 / sigma2, A, X, f64, info));
+  lr_status s = project_solve(st, n, d, m, prec, Q, L, sigma2, info, A, Z, W, Wmix, tnws);
+  if (s != LR_OK) return s;
+  LR_HIP(launch_rowmix_info(st, n, d, m, Q, Wmix, 1.0 / sigma2, A, X, prec == LR_PREC_F64, info));
   return LR_OK;
 }
 
 // ---------------------------------------------------------------- backward
 
 struct BackWs {
-  size_t off_yp, off_sk, off_tn, off_e, off_a, off_h, off_p, off_aa, off_qx, off_qb, off_xy, off_by, off_xb, off_b,
-      off_z, off_w, off_phi, off_sinv, off_scr, total;
+  size_t off_yp, off_sk, off_tn, off_za, off_wa, off_xa, off_zb, off_wb, off_xb, off_u64, off_b64, off_e, off_p,
+      off_phi, off_sinv, off_t, off_g2, off_h, off_u, off_eu, off_ca, off_aa, off_xy, off_by, off_xbm, off_u1, off_u2,
+      off_eu1, off_eu2, off_cqb, total;
 };
 
 BackWs back_layout(int64_t n, int32_t D, int32_t d, int32_t m, int32_t prec) {
   BackWs w;
   const size_t rs = real_size(prec);
-  const int mm = m > 0 ? m : 1;
+  const size_t mm = m > 0 ? (size_t)m : 1;
+  const size_t dd8 = (size_t)d * d * 8, dm8 = (size_t)d * mm * 8;
   size_t off = 0;
-  w.off_yp = off;
-  off = al(off + (size_t)n * d * rs);
-  w.off_sk = off;
-  off = al(off + sketch_ws(n, D, d, prec));
-  size_t tn = tn_workspace(n, d, d);
-  size_t t2 = tn_workspace(n, mm > d ? mm : d, mm > d ? mm : d);
-  if (t2 > tn) tn = t2;
-  w.off_tn = off;
-  off = al(off + tn);
-  w.off_e = off;
-  off = al(off + (size_t)d * d * 8);
-  w.off_a = off;
-  off = al(off + (size_t)d * 8);
-  w.off_h = off;
-  off = al(off + (size_t)d * 8);
-  w.off_p = off;
-  off = al(off + (size_t)d * d * 8);
-  w.off_aa = off;
-  off = al(off + 8);
-  w.off_qx = off;
-  off = al(off + (size_t)d * mm * 8);
-  w.off_qb = off;
-  off = al(off + (size_t)d * mm * 8);
-  w.off_xy = off;
-  off = al(off + (size_t)mm * d * 8);
-  w.off_by = off;
-  off = al(off + (size_t)mm * d * 8);
-  w.off_xb = off;
-  off = al(off + (size_t)mm * mm * 8);
-  w.off_b = off;
-  off = al(off + (size_t)n * mm * rs);
-  w.off_z = off;
-  off = al(off + (size_t)d * mm * 8);
-  w.off_w = off;
-  off = al(off + (size_t)d * mm * 8);
-  w.off_phi = off;
-  off = al(off + (size_t)d * d * 8);
-  w.off_sinv = off;
-  off = al(off + (size_t)d * d * 8);
-  w.off_scr = off;
-  off = al(off + (size_t)3 * d * d * 8);
+  auto take = [&](size_t& field, size_t bytes) {
+    field = off;
+    off = al(off + bytes);
+  };
+  take(w.off_yp, (size_t)n * d * rs);
+  take(w.off_sk, sketch_ws(n, D, d, prec));
+  const int big = (int)(mm > (size_t)d ? mm : (size_t)d);
+  take(w.off_tn, tn_workspace(n, big, big));
+  take(w.off_za, dm8);
+  take(w.off_wa, dm8);
+  take(w.off_xa, dm8);
+  take(w.off_zb, dm8);
+  take(w.off_wb, dm8);
+  take(w.off_xb, dm8);
+  take(w.off_u64, (size_t)n * mm * 8);
+  take(w.off_b64, (size_t)n * mm * 8);
+  take(w.off_e, dd8);
+  take(w.off_p, dd8);
+  take(w.off_phi, dd8);
+  take(w.off_sinv, dd8);
+  take(w.off_t, dd8);
+  take(w.off_g2, dd8);
+  take(w.off_h, (size_t)d * 8);
+  take(w.off_u, (size_t)d * 8);
+  take(w.off_eu, (size_t)d * 8);
+  take(w.off_ca, (size_t)d * 8);
+  take(w.off_aa, 8);
+  take(w.off_xy, dm8);
+  take(w.off_by, dm8);
+  take(w.off_xbm, mm * mm * 8);
+  take(w.off_u1, dm8);
+  take(w.off_u2, dm8);
+  take(w.off_eu1, dm8);
+  take(w.off_eu2, dm8);
+  take(w.off_cqb, dm8);
   w.total = off;
   return w;
+}
+
+TnOperand f64_operand(const double* p, int64_t ld) {
+  TnOperand op{};
+  op.kind = 0;
+  op.dtype = 0;
+  op.ptr = p;
+  op.ld = ld;
+  return op;
 }
 
 }  // namespace
 
 extern "C" {
 
-int32_t lr_version(void) { return (1 << 16) | 0; }
+int32_t lr_version(void) { return (2 << 16) | 0; }
 
 const char* lr_status_string(int32_t s) {
   switch (s) {
@@ -359,13 +377,14 @@ lr_status lr_lowrank_solve(void* stream, int64_t n, int32_t d, int32_t m, const 
   double* F = reinterpret_cast<double*>(base + w.off_f);
   double* Z = reinterpret_cast<double*>(base + w.off_z);
   double* W = reinterpret_cast<double*>(base + w.off_w);
+  double* Wm = reinterpret_cast<double*>(base + w.off_wm);
   void* tn = base + w.off_tn;
   const bool f64 = prec == LR_PREC_F64;
   double oscale = 1.0;
   const TnOperand om = omega_operand(omega, prec, &oscale);
   LR_HIP(launch_gemm_tn(st, n, d, d, om, real_operand(Q, d, prec), oscale, F, tn, f64));
   LR_HIP(launch_core(st, n, d, F, R, sigma2, nu, Flu, piv, C, L, logdet, info));
-  return woodbury_apply(st, n, d, m, prec, Q, L, sigma2, info, A, X, Z, W, tn);
+  return woodbury_apply(st, n, d, m, prec, Q, L, sigma2, info, A, X, Z, W, Wm, tn);
 }
 
 lr_status lr_loglik(void* stream, int64_t n, int32_t prec, const void* y, const void* alpha, const double* logdet,
@@ -384,7 +403,7 @@ size_t lr_backward_workspace_bytes(int64_t n, int32_t D, int32_t d, int32_t m, i
 
 lr_status lr_backward(void* stream, int64_t n, int32_t D, const float* X, const lr_hyper* hyp, const lr_omega* omega,
                       int32_t prec, const void* Q, const double* C, const double* L, const double* Flu,
-                      const int32_t* piv, double sigma2, int32_t mode, int32_t m, const void* U, const void* V,
+                      const int32_t* piv, double sigma2, int32_t mode, int32_t m, const void* A, const void* V,
                       const void* Yprime, double* dtheta, void* dA, void* ws, size_t ws_bytes) {
   if (!valid_prec(prec)) return LR_ERR_ARG;
   if (D < 1 || D > 15) return LR_ERR_SHAPE;
@@ -399,16 +418,14 @@ lr_status lr_backward(void* stream, int64_t n, int32_t D, const float* X, const 
   if (mode == 1 && (m < 1 || m > 64)) return LR_ERR_SHAPE;
   if (!is_fin(sigma2) || !(sigma2 > 0.0)) return LR_ERR_ARG;
   if (X == nullptr || Q == nullptr || C == nullptr || L == nullptr || Flu == nullptr || piv == nullptr ||
-      U == nullptr || dtheta == nullptr || (mode == 1 && V == nullptr))
+      A == nullptr || dtheta == nullptr || (mode == 1 && V == nullptr))
     return LR_ERR_ARG;
   const BackWs w = back_layout(n, D, d, m, prec);
   if ((s = check_ws(w.total, ws, ws_bytes)) != LR_OK) return s;
 
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
-  const bool f64 = prec == LR_PREC_F64;
-  const size_t rs = real_size(prec);
-  (void)rs;
+  auto dptr = [&](size_t off) { return reinterpret_cast<double*>(base + off); };
   void* tn = base + w.off_tn;
   const void* yp = Yprime;
   if (yp == nullptr) {
@@ -421,69 +438,95 @@ lr_status lr_backward(void* stream, int64_t n, int32_t D, const float* X, const 
   const TnOperand om = omega_operand(omega, prec, &oscale);
   const TnOperand ypo = real_operand(yp, d, prec);
   const TnOperand qo = real_operand(Q, d, prec);
-  BackwardSmall b{};
+  const double inv_s2 = 1.0 / sigma2;
+  // every n-length product below sums exact products in float64
+  double* E = dptr(w.off_e);
+  double* Phi = dptr(w.off_phi);
+  LR_HIP(launch_gemm_tn(st, n, d, d, om, ypo, oscale, E, tn, true));
+  LR_HIP(launch_trsm_cols(st, false, d, d, Flu, piv, 2, nullptr, Phi, d, nullptr));
+
+  BackwardScalars b{};
   b.mode = mode;
   b.n = n;
   b.d = d;
   b.m = m;
   b.sigma2 = sigma2;
-  b.Flu = Flu;
+  b.E = E;
   b.C = C;
-  b.L = L;
-  b.piv = piv;
-  b.E = reinterpret_cast<double*>(base + w.off_e);
-  b.scratch = reinterpret_cast<double*>(base + w.off_scr);
   b.dtheta = dtheta;
-  double* phi = reinterpret_cast<double*>(base + w.off_phi);
-  LR_HIP(launch_identity(st, phi, d));
-  LR_HIP(launch_solve_cols(st, 0, d, d, Flu, piv, nullptr, phi, d, nullptr));
-  b.Phi = phi;
+  double* za = dptr(w.off_za);
+  double* wa = dptr(w.off_wa);
+  double* xa = dptr(w.off_xa);
+  double* u64 = dptr(w.off_u64);
+  // a = S^{-1} Q^T A, and alpha (or X) = K~^{-1} A recomputed in float64
+  if ((s = project_solve(st, n, d, m, prec, Q, L, sigma2, nullptr, A, za, wa, xa, tn)) != LR_OK) return s;
+  LR_HIP(launch_rowmix_f64out(st, n, d, m, Q, xa, inv_s2, A, u64, prec == LR_PREC_F64));
+  const TnOperand uo = f64_operand(u64, m);
   if (mode == 0) {
-    double* sinv = reinterpret_cast<double*>(base + w.off_sinv);
-    LR_HIP(launch_identity(st, sinv, d));
-    LR_HIP(launch_solve_cols(st, 1, d, d, L, nullptr, nullptr, sinv, d, nullptr));
-    b.Sinv = sinv;
-  }
-  LR_HIP(launch_gemm_tn(st, n, d, d, om, ypo, oscale, const_cast<double*>(b.E), tn, f64));
-  if (mode == 0) {
-    const TnOperand al_ = real_operand(U, 1, prec);
-    double* a = reinterpret_cast<double*>(base + w.off_a);
-    double* h = reinterpret_cast<double*>(base + w.off_h);
-    double* P = reinterpret_cast<double*>(base + w.off_p);
-    double* aa = reinterpret_cast<double*>(base + w.off_aa);
-    LR_HIP(launch_gemm_tn(st, n, d, 1, qo, al_, 1.0, a, tn, f64));
-    LR_HIP(launch_gemm_tn(st, n, d, 1, ypo, al_, 1.0, h, tn, f64));
-    LR_HIP(launch_gemm_tn(st, n, d, d, qo, ypo, 1.0, P, tn, f64));
-    LR_HIP(launch_gemm_tn(st, n, 1, 1, al_, al_, 1.0, aa, tn, f64));
-    b.a = a;
+    double* P = dptr(w.off_p);
+    double* Sinv = dptr(w.off_sinv);
+    double* T = dptr(w.off_t);
+    double* G2 = dptr(w.off_g2);
+    double* h = dptr(w.off_h);
+    double* u = dptr(w.off_u);
+    double* Eu = dptr(w.off_eu);
+    double* Ca = dptr(w.off_ca);
+    double* aa = dptr(w.off_aa);
+    LR_HIP(launch_gemm_tn(st, n, d, 1, ypo, uo, 1.0, h, tn, true));
+    LR_HIP(launch_gemm_tn(st, n, 1, 1, uo, uo, 1.0, aa, tn, true));
+    LR_HIP(launch_gemm_tn(st, n, d, d, qo, ypo, 1.0, P, tn, true));
+    LR_HIP(launch_trsm_cols(st, true, d, d, L, nullptr, 2, nullptr, Sinv, d, nullptr));
+    LR_HIP(launch_gemm_dd(st, d, 1, d, 1.0, Phi, d, true, wa, 1, false, 0.0, u, 1));
+    LR_HIP(launch_gemm_dd(st, d, d, d, 1.0, Sinv, d, false, Phi, d, false, 0.0, T, d));
+    LR_HIP(launch_gemm_dd(st, d, d, d, 1.0, Phi, d, true, T, d, false, 0.0, G2, d));
+    LR_HIP(launch_gemm_dd(st, d, 1, d, 1.0, E, d, false, u, 1, false, 0.0, Eu, 1));
+    LR_HIP(launch_gemm_dd(st, d, 1, d, 1.0, C, d, false, wa, 1, false, 0.0, Ca, 1));
+    b.a = wa;
     b.h = h;
-    b.P = P;
     b.aa = aa;
+    b.u = u;
+    b.Eu = Eu;
+    b.Ca = Ca;
+    b.T = T;
+    b.P = P;
+    b.G2 = G2;
+    b.Sinv = Sinv;
   } else {
-    void* B = dA != nullptr ? dA : (void*)(base + w.off_b);
-    double* Zb = reinterpret_cast<double*>(base + w.off_z);
-    double* Wb = reinterpret_cast<double*>(base + w.off_w);
-    s = woodbury_apply(st, n, d, m, prec, Q, L, sigma2, nullptr, V, B, Zb, Wb, tn);
-    if (s != LR_OK) return s;
-    const TnOperand xo = real_operand(U, m, prec);
-    const TnOperand bo = real_operand(B, m, prec);
-    double* QX = reinterpret_cast<double*>(base + w.off_qx);
-    double* QB = reinterpret_cast<double*>(base + w.off_qb);
-    double* XY = reinterpret_cast<double*>(base + w.off_xy);
-    double* BY = reinterpret_cast<double*>(base + w.off_by);
-    double* XB = reinterpret_cast<double*>(base + w.off_xb);
-    LR_HIP(launch_gemm_tn(st, n, d, m, qo, xo, 1.0, QX, tn, f64));
-    LR_HIP(launch_gemm_tn(st, n, d, m, qo, bo, 1.0, QB, tn, f64));
-    LR_HIP(launch_gemm_tn(st, n, m, d, xo, ypo, 1.0, XY, tn, f64));
-    LR_HIP(launch_gemm_tn(st, n, m, d, bo, ypo, 1.0, BY, tn, f64));
-    LR_HIP(launch_gemm_tn(st, n, m, m, xo, bo, 1.0, XB, tn, f64));
-    b.QX = QX;
-    b.QB = QB;
+    double* zb = dptr(w.off_zb);
+    double* wb = dptr(w.off_wb);
+    double* xb = dptr(w.off_xb);
+    double* b64 = dptr(w.off_b64);
+    double* XY = dptr(w.off_xy);
+    double* BY = dptr(w.off_by);
+    double* XB = dptr(w.off_xbm);
+    double* U1 = dptr(w.off_u1);
+    double* U2 = dptr(w.off_u2);
+    double* EU1 = dptr(w.off_eu1);
+    double* EU2 = dptr(w.off_eu2);
+    double* CQB = dptr(w.off_cqb);
+    if ((s = project_solve(st, n, d, m, prec, Q, L, sigma2, nullptr, V, zb, wb, xb, tn)) != LR_OK) return s;
+    LR_HIP(launch_rowmix_f64out(st, n, d, m, Q, xb, inv_s2, V, b64, prec == LR_PREC_F64));
+    if (dA != nullptr) LR_HIP(launch_rowmix_info(st, n, d, m, Q, xb, inv_s2, V, dA, prec == LR_PREC_F64, nullptr));
+    const TnOperand bo = f64_operand(b64, m);
+    LR_HIP(launch_gemm_tn(st, n, m, d, uo, ypo, 1.0, XY, tn, true));
+    LR_HIP(launch_gemm_tn(st, n, m, d, bo, ypo, 1.0, BY, tn, true));
+    LR_HIP(launch_gemm_tn(st, n, m, m, uo, bo, 1.0, XB, tn, true));
+    LR_HIP(launch_gemm_dd(st, d, m, d, 1.0, Phi, d, true, wa, m, false, 0.0, U1, m));
+    LR_HIP(launch_gemm_dd(st, d, m, d, 1.0, Phi, d, true, wb, m, false, 0.0, U2, m));
+    LR_HIP(launch_gemm_dd(st, d, m, d, 1.0, E, d, false, U1, m, false, 0.0, EU1, m));
+    LR_HIP(launch_gemm_dd(st, d, m, d, 1.0, E, d, false, U2, m, false, 0.0, EU2, m));
+    LR_HIP(launch_gemm_dd(st, d, m, d, 1.0, C, d, false, wb, m, false, 0.0, CQB, m));
+    b.U1 = U1;
+    b.U2 = U2;
+    b.EU1 = EU1;
+    b.EU2 = EU2;
+    b.QX = wa;
+    b.CQB = CQB;
     b.XY = XY;
     b.BY = BY;
     b.XB = XB;
   }
-  LR_HIP(launch_backward_small(st, b));
+  LR_HIP(launch_backward_scalars(st, b));
   return LR_OK;
 }
 

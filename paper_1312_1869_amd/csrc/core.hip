@@ -3,14 +3,14 @@
 // Forward (d <= 1024):
 //   blocked LU with partial pivoting of F = Omega^T Q (LAPACK getrf
 //   convention: whole rows swapped, first index of the largest magnitude as
-//   pivot); C = F^{-1} R^T by forward/backward substitution, one wave per
-//   right-hand side; C <- (C + C^T)/2, S = C + (sigma2 - nu) I, blocked
+//   pivot); C = F^{-1} R^T by blocked forward/backward substitution; C <- (C + C^T)/2, S = C + (sigma2 - nu) I, blocked
 //   Cholesky S = L L^T and log|K~| = (n - d) log sigma2 + 2 sum log L_jj.
 //   info = -k for a zero LU pivot at step k, k for the k-th non-positive
 //   Cholesky pivot (1-based), 0 on success.
-// The small solve W' = S^{-1} Z - Z / sigma2 uses the same column solver.
-// The backward kernel evaluates the d x d contractions of the hyperparameter
-// adjoint (formulas in lrinv.h / the oracle's grad module).
+// The solves with many right-hand sides (F^{-1} R^T, S^{-1} Z) are the blocked
+// ones of dense.hip. The backward kernel adds up the contractions of the
+// hyperparameter adjoint from the d x d and d x m products the host sequence
+// forms with them.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -379,103 +379,6 @@ __global__ void init_info_kernel(const double* __restrict__ F, double* Flu, int6
   if (e == 0) *info = 0;
 }
 
-// Solve in place, for every column c of X (d x nrhs, leading dimension ldx):
-//   mode 0: X <- A^{-1} X with A = P L U from the blocked LU (pivots applied first);
-//   mode 1: X <- S^{-1} X with S = L L^T (lower Cholesky factor);
-//   mode 2: as 0, with the right-hand side read as B[c][i] = src[c * d + i]
-//           (i.e. the solve of A X = src^T), written to X.
-// One wave per column; the column lives in LDS; the next row of the factor is
-// prefetched into registers while the current row's dot product completes.
-// Skipped when *info != 0.
-constexpr int kSolveWaves = 4;
-constexpr int kSolvePer = 16;  // d / 64 rounded up, d <= 1024
-
-template <bool UNIT, bool LOWER, bool TRANSF>
-__device__ __forceinline__ void wave_trisolve(const double* __restrict__ Fm, int d, double* y, int lane) {
-  // LOWER: y_i = (y_i - sum_{k<i} F[i][k] y_k) / (UNIT ? 1 : F[i][i])
-  // !LOWER with TRANSF: y_i = (y_i - sum_{k>i} F[k][i] y_k) / F[i][i]   (F^T upper)
-  // !LOWER without TRANSF: y_i = (y_i - sum_{k>i} F[i][k] y_k) / F[i][i]
-  double nxt[kSolvePer];
-  auto load_row = [&](int i, double (&buf)[kSolvePer]) {
-#pragma unroll
-    for (int q = 0; q < kSolvePer; ++q) {
-      const int k = lane + 64 * q;
-      bool use;
-      if (LOWER) use = k < i;
-      else use = k > i && k < d;
-      buf[q] = use ? (TRANSF ? Fm[(int64_t)k * d + i] : Fm[(int64_t)i * d + k]) : 0.0;
-    }
-  };
-  const int first = LOWER ? 0 : d - 1;
-  const int step = LOWER ? 1 : -1;
-  load_row(first, nxt);
-  for (int it = 0; it < d; ++it) {
-    const int i = first + step * it;
-    double cur[kSolvePer];
-#pragma unroll
-    for (int q = 0; q < kSolvePer; ++q) cur[q] = nxt[q];
-    if (it + 1 < d) load_row(i + step, nxt);
-    double part = 0.0;
-#pragma unroll
-    for (int q = 0; q < kSolvePer; ++q) {
-      const int k = lane + 64 * q;
-      if (k < d) part += cur[q] * y[k];
-    }
-    part = wave_sum(part);
-    const double diag = UNIT ? 1.0 : Fm[(int64_t)i * d + i];
-    const double yi = (y[i] - part) / diag;
-    __builtin_amdgcn_wave_barrier();
-    if (lane == 0) y[i] = yi;
-    __builtin_amdgcn_wave_barrier();
-  }
-}
-
-__global__ __launch_bounds__(64 * kSolveWaves) void solve_cols_kernel(int mode, int d, int nrhs, const double* Fm,
-                                                                      const int32_t* __restrict__ piv,
-                                                                      const double* __restrict__ src, double* X,
-                                                                      int ldx, const int32_t* __restrict__ info) {
-  extern __shared__ double ybuf[];
-  if (info != nullptr && *info != 0) return;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int c = blockIdx.x * kSolveWaves + w;
-  if (c >= nrhs) return;
-  double* y = ybuf + (int64_t)w * d;
-  for (int i = lane; i < d; i += 64) y[i] = (mode == 2) ? src[(int64_t)c * d + i] : X[(int64_t)i * ldx + c];
-  __builtin_amdgcn_wave_barrier();
-  if (mode != 1) {
-    if (lane == 0) {
-      for (int k = 0; k < d; ++k) {
-        const int p = piv[k];
-        if (p != k) {
-          const double tmp = y[k];
-          y[k] = y[p];
-          y[p] = tmp;
-        }
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
-    wave_trisolve<true, true, false>(Fm, d, y, lane);   // unit lower L
-    wave_trisolve<false, false, false>(Fm, d, y, lane); // upper U
-  } else {
-    wave_trisolve<false, true, false>(Fm, d, y, lane);  // L
-    wave_trisolve<false, false, true>(Fm, d, y, lane);  // L^T
-  }
-  __builtin_amdgcn_wave_barrier();
-  for (int i = lane; i < d; i += 64) X[(int64_t)i * ldx + c] = y[i];
-}
-
-hipError_t launch_solve_cols(hipStream_t st, int mode, int d, int nrhs, const double* Fm, const int32_t* piv,
-                             const double* src, double* X, int ldx, const int32_t* info) {
-  if (nrhs <= 0) return hipSuccess;
-  const size_t lds = (size_t)kSolveWaves * d * sizeof(double);
-  hipError_t e = hipFuncSetAttribute((const void*)solve_cols_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(solve_cols_kernel, dim3((unsigned)((nrhs + kSolveWaves - 1) / kSolveWaves)),
-                     dim3(64 * kSolveWaves), lds, st, mode, d, nrhs, Fm, piv, src, X, ldx, info);
-  return hipGetLastError();
-}
-
 hipError_t launch_core(hipStream_t st, int64_t n, int d, const double* F, const double* R, double sigma2, double nu,
                        double* Flu, int32_t* piv, double* C, double* L, double* logdet, int32_t* info) {
   const int64_t dd = (int64_t)d * d;
@@ -504,7 +407,7 @@ hipError_t launch_core(hipStream_t st, int64_t n, int d, const double* F, const 
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // C = F^{-1} R^T: column c of R^T is row c of R
-  if ((e = launch_solve_cols(st, 2, d, d, Flu, piv, R, C, d, info)) != hipSuccess) return e;
+  if ((e = launch_trsm_cols(st, false, d, d, Flu, piv, 1, R, C, d, info)) != hipSuccess) return e;
   hipLaunchKernelGGL(shift_lower_kernel, dim3(ddb), dim3(256), 0, st, d, sigma2, nu, C, L, info);
   hipLaunchKernelGGL(sym_kernel, dim3(ddb), dim3(256), 0, st, d, C, info);
   for (int k0 = 0; k0 < d; k0 += kPanel) {
@@ -559,119 +462,82 @@ hipError_t launch_loglik(hipStream_t st, int64_t n, bool f64, const void* y, con
 
 // ------------------------------------------------------------------ S^{-1} Z
 
-__global__ void sub_scaled_kernel(int64_t count, const double* __restrict__ Z, double inv_sigma2,
-                                  const int32_t* __restrict__ info, double* __restrict__ W) {
-  if (info != nullptr && *info != 0) return;
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx < count) W[idx] -= Z[idx] * inv_sigma2;
-}
-
 hipError_t launch_core_apply(hipStream_t st, int d, int m, const double* L, const double* Z, double sigma2,
-                             const int32_t* info, double* Wout) {
+                             const int32_t* info, double* Wfull, double* Wmix) {
   if (m <= 0) return hipSuccess;
-  const int64_t count = (int64_t)d * m;
-  hipError_t e = hipMemcpyAsync(Wout, Z, (size_t)count * sizeof(double), hipMemcpyDeviceToDevice, st);
+  hipError_t e = launch_trsm_cols(st, true, d, m, L, nullptr, 3, Z, Wfull, m, info);
   if (e != hipSuccess) return e;
-  e = launch_solve_cols(st, 1, d, m, L, nullptr, nullptr, Wout, m, info);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(sub_scaled_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count, Z,
-                     1.0 / sigma2, info, Wout);
-  return hipGetLastError();
+  return launch_wmix(st, (int64_t)d * m, Wfull, Z, sigma2, info, Wmix);
 }
 
-// ------------------------------------------------------------------ backward d x d
+// ------------------------------------------------------------------ backward scalars
 
-// out = A B (d x d), all row-major in global memory.
-__device__ void matmul_dd(const double* A, const double* B, double* out, int d) {
-  const int64_t dd = (int64_t)d * d;
-  for (int64_t e = threadIdx.x; e < dd; e += kCoreThreads) {
-    const int i = (int)(e / d), j = (int)(e % d);
-    double s = 0.0;
-    for (int k = 0; k < d; ++k) s += A[(int64_t)i * d + k] * B[(int64_t)k * d + j];
-    out[e] = s;
-  }
-}
-
-__global__ __launch_bounds__(kCoreThreads) void backward_small_kernel(BackwardSmall b) {
+// Contractions of the adjoint from the d x d and d x m products (one workgroup):
+//   log-likelihood: u = Phi^T a, T = S^{-1} Phi, G2 = Phi^T S^{-1} Phi,
+//     d/dlog ell    = u.h - <T, P> - (u.E u - <G2, E>) / 2
+//     d/dlog s      = a.C a - <S^{-1}, C>
+//     d/dlog sigma2 = sigma2 (alpha^T alpha - (n - d) / sigma2 - tr S^{-1}) / 2
+//   solve: U1 = Phi^T QX, U2 = Phi^T QB,
+//     d/dlog ell    = -(<U2, XY^T> + <U1, BY^T>) + (<U1, E U2> + <U2, E U1>) / 2
+//     d/dlog s      = -2 <QX, C QB>
+//     d/dlog sigma2 = -sigma2 tr(X^T B)
+__global__ __launch_bounds__(kCoreThreads) void backward_scalars_kernel(BackwardScalars b) {
   __shared__ double red[kCoreWaves];
   const int t = threadIdx.x;
   const int d = b.d;
   const int64_t dd = (int64_t)d * d;
-  const double* Phi = b.Phi;          // F^{-1} (precomputed)
-  double* Mq = b.scratch;             // Q^T G Q
-  double* T1 = b.scratch + dd;        // work
-  double* T2 = b.scratch + 2 * dd;    // work
-
-  double dlogell_t1 = 0.0, trace_g = 0.0;
   if (b.mode == 0) {
-    const double* Sinv = b.Sinv;      // S^{-1} (precomputed)
-    // Mq = (a a^T - S^{-1}) / 2 ; tr S^{-1}
-    double tr = 0.0;
-    for (int64_t e = t; e < dd; e += kCoreThreads) {
-      const int i = (int)(e / d), j = (int)(e % d);
-      Mq[e] = 0.5 * (b.a[i] * b.a[j] - Sinv[e]);
-      if (i == j) tr += Sinv[e];
-    }
-    const double tr_sinv = block_sum(tr, red);
-    // (Phi^T a) . h
-    double p1 = 0.0;
+    double p_uh = 0.0, p_uEu = 0.0, p_aCa = 0.0, p_tr = 0.0;
     for (int i = t; i < d; i += kCoreThreads) {
-      double u = 0.0;
-      for (int k = 0; k < d; ++k) u += Phi[(int64_t)k * d + i] * b.a[k];
-      p1 += u * b.h[i];
+      p_uh += b.u[i] * b.h[i];
+      p_uEu += b.u[i] * b.Eu[i];
+      p_aCa += b.a[i] * b.Ca[i];
+      p_tr += b.Sinv[(int64_t)i * d + i];
     }
-    const double t1a = block_sum(p1, red);
-    __syncthreads();
-    // <S^{-1} Phi, P>
-    matmul_dd(Sinv, Phi, T2, d);
-    __syncthreads();
-    double p2 = 0.0;
-    for (int64_t e = t; e < dd; e += kCoreThreads) p2 += T2[e] * b.P[e];
-    const double t1b = block_sum(p2, red);
-    dlogell_t1 = t1a - t1b;
-    trace_g = 0.5 * (b.aa[0] - ((double)(b.n - d) / b.sigma2 + tr_sinv));
+    double p_tp = 0.0, p_ge = 0.0, p_sc = 0.0;
+    for (int64_t e = t; e < dd; e += kCoreThreads) {
+      p_tp += b.T[e] * b.P[e];
+      p_ge += b.G2[e] * b.E[e];
+      p_sc += b.Sinv[e] * b.C[e];
+    }
+    const double uh = block_sum(p_uh, red);
+    const double uEu = block_sum(p_uEu, red);
+    const double aCa = block_sum(p_aCa, red);
+    const double trs = block_sum(p_tr, red);
+    const double tp = block_sum(p_tp, red);
+    const double ge = block_sum(p_ge, red);
+    const double sc = block_sum(p_sc, red);
+    if (t == 0) {
+      const double t2 = 0.5 * (uEu - ge);
+      b.dtheta[0] = uh - tp - t2;
+      b.dtheta[1] = aCa - sc;
+      b.dtheta[2] = b.sigma2 * 0.5 * (b.aa[0] - ((double)(b.n - d) / b.sigma2 + trs));
+    }
   } else {
     const int m = b.m;
-    // Mq = -(QX QB^T + QB QX^T)/2 ; T1 = QB XY + QX BY
-    for (int64_t e = t; e < dd; e += kCoreThreads) {
-      const int i = (int)(e / d), j = (int)(e % d);
-      double s1 = 0.0, s2 = 0.0;
-      for (int c = 0; c < m; ++c) {
-        s1 += b.QX[(int64_t)i * m + c] * b.QB[(int64_t)j * m + c] + b.QB[(int64_t)i * m + c] * b.QX[(int64_t)j * m + c];
-        s2 += b.QB[(int64_t)i * m + c] * b.XY[(int64_t)c * d + j] + b.QX[(int64_t)i * m + c] * b.BY[(int64_t)c * d + j];
-      }
-      Mq[e] = -0.5 * s1;
-      T1[e] = s2;
+    const int64_t dm = (int64_t)d * m;
+    double p_t1 = 0.0, p_t2 = 0.0, p_mc = 0.0, p_xb = 0.0;
+    for (int64_t e = t; e < dm; e += kCoreThreads) {
+      const int i = (int)(e / m), c = (int)(e % m);
+      p_t1 += b.U2[e] * b.XY[(int64_t)c * d + i] + b.U1[e] * b.BY[(int64_t)c * d + i];
+      p_t2 += b.U1[e] * b.EU2[e] + b.U2[e] * b.EU1[e];
+      p_mc += b.QX[e] * b.CQB[e];
     }
-    __syncthreads();
-    double p = 0.0;
-    for (int64_t e = t; e < dd; e += kCoreThreads) p += Phi[e] * T1[e];
-    dlogell_t1 = -block_sum(p, red);
-    double tr = 0.0;
-    for (int c = t; c < m; c += kCoreThreads) tr += b.XB[(int64_t)c * m + c];
-    trace_g = -block_sum(tr, red);
-  }
-  __syncthreads();
-  // T2' = <Mq Phi, Phi E>
-  matmul_dd(Mq, Phi, T1, d);
-  matmul_dd(Phi, b.E, T2, d);
-  __syncthreads();
-  double p3 = 0.0, p4 = 0.0;
-  for (int64_t e = t; e < dd; e += kCoreThreads) {
-    p3 += T1[e] * T2[e];
-    p4 += Mq[e] * b.C[e];
-  }
-  const double t2 = block_sum(p3, red);
-  const double mc = block_sum(p4, red);
-  if (t == 0) {
-    b.dtheta[0] = dlogell_t1 - t2;
-    b.dtheta[1] = 2.0 * mc;
-    b.dtheta[2] = b.sigma2 * trace_g;
+    for (int c = t; c < m; c += kCoreThreads) p_xb += b.XB[(int64_t)c * m + c];
+    const double t1 = block_sum(p_t1, red);
+    const double t2 = block_sum(p_t2, red);
+    const double mc = block_sum(p_mc, red);
+    const double xb = block_sum(p_xb, red);
+    if (t == 0) {
+      b.dtheta[0] = -t1 + 0.5 * t2;
+      b.dtheta[1] = -2.0 * mc;
+      b.dtheta[2] = -b.sigma2 * xb;
+    }
   }
 }
 
-hipError_t launch_backward_small(hipStream_t st, const BackwardSmall& b) {
-  hipLaunchKernelGGL(backward_small_kernel, dim3(1), dim3(kCoreThreads), 0, st, b);
+hipError_t launch_backward_scalars(hipStream_t st, const BackwardScalars& b) {
+  hipLaunchKernelGGL(backward_scalars_kernel, dim3(1), dim3(kCoreThreads), 0, st, b);
   return hipGetLastError();
 }
 

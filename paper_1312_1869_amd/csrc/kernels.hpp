@@ -47,44 +47,69 @@ hipError_t launch_rowmix(hipStream_t st, int64_t n, int d, int m, const void* Q,
                          const void* A, void* out, bool f64);
 hipError_t launch_rowmix_info(hipStream_t st, int64_t n, int d, int m, const void* Q, const double* W, double alpha,
                               const void* A, void* out, bool f64, const int32_t* info);
+// out (n x m, float64) = alpha A + Q W for real (float or double) Q and A: the
+// products and sums in float64 on float64 matrix cores.
+hipError_t launch_rowmix_f64out(hipStream_t st, int64_t n, int d, int m, const void* Q, const double* W,
+                                double alpha, const void* A, double* out, bool in_f64);
+// out (n x m, float) = float(in), in float64.
+hipError_t launch_narrow(hipStream_t st, int64_t count, const double* in, float* out);
+// out = W - Z / sigma2 (count doubles); skipped when *info != 0.
+hipError_t launch_wmix(hipStream_t st, int64_t count, const double* W, const double* Z, double sigma2,
+                       const int32_t* info, double* out);
 hipError_t launch_fill(hipStream_t st, double* out, int64_t count, double v);
 
 // core.hip
 hipError_t launch_core(hipStream_t st, int64_t n, int d, const double* F, const double* R, double sigma2, double nu,
                        double* Flu, int32_t* piv, double* C, double* L, double* logdet, int32_t* info);
-// W' = S^{-1} Z - Z / sigma2 (d x m), S = L L^T; skipped when *info != 0.
+// Wfull = S^{-1} Z and Wmix = Wfull - Z / sigma2 (d x m), S = L L^T; skipped
+// when *info != 0.
 hipError_t launch_core_apply(hipStream_t st, int d, int m, const double* L, const double* Z, double sigma2,
-                             const int32_t* info, double* Wout);
+                             const int32_t* info, double* Wfull, double* Wmix);
 hipError_t launch_loglik(hipStream_t st, int64_t n, bool f64, const void* y, const void* alpha, const double* logdet,
                          const int32_t* info, double* out);
-// Backward small d x d work (see lr_backward).
-struct BackwardSmall {
+// Scalars of the hyperparameter adjoint (see lr_backward and dense.hip).
+struct BackwardScalars {
   int mode;
   int64_t n;
   int d, m;
   double sigma2;
-  const double *Flu, *C, *L;
-  const int32_t* piv;
-  const double* a;      // mode 0: Q^T alpha (d)
-  const double* h;      // mode 0: Y'^T alpha (d)
-  const double* P;      // mode 0: Q^T Y' (d x d)
+  // mode 0 (log-likelihood)
+  const double* a;      // S^{-1} Q^T y (d)
+  const double* h;      // Y'^T alpha (d)
+  const double* aa;     // alpha^T alpha (1)
+  const double* u;      // Phi^T a (d)
+  const double* Eu;     // E u (d)
+  const double* Ca;     // C a (d)
+  const double* T;      // S^{-1} Phi (d x d)
+  const double* P;      // Q^T Y' (d x d)
+  const double* G2;     // Phi^T S^{-1} Phi (d x d)
   const double* E;      // Omega^T Y' (d x d)
-  const double* aa;     // mode 0: alpha^T alpha (1)
-  const double* QX;     // mode 1: Q^T X (d x m)
-  const double* QB;     // mode 1: Q^T B (d x m)
-  const double* XY;     // mode 1: X^T Y' (m x d)
-  const double* BY;     // mode 1: B^T Y' (m x d)
-  const double* XB;     // mode 1: X^T B (m x m)
-  const double* Phi;    // F^{-1} (d x d)
-  const double* Sinv;   // mode 0: S^{-1} (d x d)
-  double* scratch;      // 3 d*d doubles
+  const double* Sinv;   // S^{-1} (d x d)
+  const double* C;      // C (d x d)
+  // mode 1 (solve)
+  const double* U1;     // Phi^T QX (d x m), QX = S^{-1} Q^T A
+  const double* U2;     // Phi^T QB (d x m), QB = S^{-1} Q^T Abar
+  const double* EU1;    // E U1 (d x m)
+  const double* EU2;    // E U2 (d x m)
+  const double* QX;     // (d x m)
+  const double* CQB;    // C QB (d x m)
+  const double* XY;     // X^T Y' (m x d)
+  const double* BY;     // B^T Y' (m x d)
+  const double* XB;     // X^T B (m x m)
   double* dtheta;
 };
-hipError_t launch_backward_small(hipStream_t st, const BackwardSmall& b);
-// Column-wise dense solves (see core.hip): mode 0 LU (P L U), 1 Cholesky (L L^T),
-// 2 LU with the right-hand side read transposed from src. Skipped when *info != 0.
-hipError_t launch_solve_cols(hipStream_t st, int mode, int d, int nrhs, const double* Fm, const int32_t* piv,
-                             const double* src, double* X, int ldx, const int32_t* info);
+hipError_t launch_backward_scalars(hipStream_t st, const BackwardScalars& b);
+// dense.hip: out = alpha op(A) op(B) + beta out (row-major float64).
+hipError_t launch_gemm_dd(hipStream_t st, int M, int N, int K, double alpha, const double* A, int lda, bool ta,
+                          const double* B, int ldb, bool tb, double beta, double* out, int ldo);
+// dense.hip: blocked solves with nrhs right-hand sides (d <= 1024), written to X
+// (d x nrhs, leading dimension ldx). chol = false: X <- U^{-1} L^{-1} P B with the
+// getrf factors Fm/piv; chol = true: X <- L^{-T} L^{-1} B, Fm = L lower.
+// src_kind: 0 = B is X, 1 = column c of B is row c of src (d x d), 2 = B = I,
+// 3 = B is src (d x nrhs, leading dimension ldx).
+// Skipped when *info != 0.
+hipError_t launch_trsm_cols(hipStream_t st, bool chol, int d, int nrhs, const double* Fm, const int32_t* piv,
+                            int src_kind, const double* src, double* X, int ldx, const int32_t* info);
 hipError_t launch_identity(hipStream_t st, double* X, int d);
 
 }  // namespace lr

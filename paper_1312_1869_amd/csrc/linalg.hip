@@ -9,8 +9,8 @@
 //    to a float64 accumulator; chunk partials are float64 and are summed in a
 //    fixed order. The SRHT operand is generated from its sign/column
 //    description: X(r, k) = signs[r] (-1)^popcount(r & cols[k]) (times c).
-//  * rowmix: out = alpha A + Q W, W d x m (float64, staged in LDS as the
-//    working precision), one wave per 16 rows x 16 columns.
+//  * rowmix: out = alpha A + Q W, W d x m float64, one wave per 16 rows x 16
+//    columns, products and sums in float64 with one rounding at the end.
 #include <type_traits>
 
 #include "common.hpp"
@@ -417,45 +417,40 @@ hipError_t launch_gemm_tn(hipStream_t st, int64_t n, int M, int N, const TnOpera
 
 // ------------------------------------------------------------------ rowmix
 
-template <typename R>
-__global__ __launch_bounds__(256) void rowmix_kernel(int64_t n, int d, int m, const R* __restrict__ Q,
-                                                     const double* __restrict__ W, R alpha,
-                                                     const R* __restrict__ A, R* __restrict__ out,
+// out = alpha A + Q W with the products and sums in float64 (float64 matrix
+// cores; float inputs are exact in float64) and one rounding to RO at the
+// end. W (d x m, float64) is read straight from L2: 16 lanes read 16
+// consecutive entries of a row of W.
+template <typename RI, typename RO>
+__global__ __launch_bounds__(256) void rowmix_kernel(int64_t n, int d, int m, const RI* __restrict__ Q,
+                                                     const double* __restrict__ W, double alpha,
+                                                     const RI* __restrict__ A, RO* __restrict__ out,
                                                      const int32_t* __restrict__ info) {
-  using Acc = typename std::conditional<sizeof(R) == 4, f32x4_t, f64x4_t>::type;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  R* Ws = reinterpret_cast<R*>(smem_raw);  // d x 16
   if (info != nullptr && *info != 0) return;
-  const int c0 = blockIdx.y * 16;
-  for (int idx = threadIdx.x; idx < d * 16; idx += blockDim.x) {
-    const int k = idx / 16, c = idx % 16;
-    Ws[idx] = (c0 + c < m) ? (R)W[(int64_t)k * m + c0 + c] : (R)0;
-  }
-  __syncthreads();
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int fl = lane & 15, fg = lane >> 4;
   const int64_t row0 = (int64_t)blockIdx.x * 64 + w * 16;
   const int64_t arow = row0 + fl;
   const bool row_ok = arow < n;
-  Acc acc;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) acc[i] = 0;
+  const int col = blockIdx.y * 16 + fl;
+  const bool col_ok = col < m;
+  f64x4_t acc = f64x4_t{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < d; k0 += 32) {
-    Frag8<R> a, b;
+    double a[8], b[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int k = k0 + 8 * fg + e;
-      a.v[e] = (row_ok && k < d) ? Q[arow * d + k] : (R)0;
-      b.v[e] = (k < d) ? Ws[k * 16 + fl] : (R)0;
+      a[e] = (row_ok && k < d) ? (double)Q[arow * d + k] : 0.0;
+      b[e] = (col_ok && k < d) ? W[(int64_t)k * m + col] : 0.0;
     }
-    mfma8<R>(acc, a, b);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[e], b[e], acc, 0, 0, 0);
   }
-  const int col = c0 + fl;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int64_t row = row0 + acc_row<Acc>(fg, i);
-    if (row < n && col < m) out[row * m + col] = alpha * A[row * m + col] + (R)acc[i];
+    const int64_t row = row0 + acc_row<f64x4_t>(fg, i);
+    if (row < n && col_ok) out[row * m + col] = (RO)(alpha * (double)A[row * m + col] + acc[i]);
   }
 }
 
@@ -468,21 +463,51 @@ hipError_t launch_rowmix_info(hipStream_t st, int64_t n, int d, int m, const voi
                               const void* A, void* out, bool f64, const int32_t* info) {
   if (m <= 0 || n <= 0) return hipSuccess;
   dim3 grid((unsigned)((n + 63) / 64), (unsigned)((m + 15) / 16));
-  if (f64) {
-    const size_t lds = (size_t)d * 16 * sizeof(double);
-    hipError_t e = hipFuncSetAttribute((const void*)rowmix_kernel<double>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(rowmix_kernel<double>, grid, dim3(256), lds, st, n, d, m, (const double*)Q, W, alpha,
+  if (f64)
+    hipLaunchKernelGGL((rowmix_kernel<double, double>), grid, dim3(256), 0, st, n, d, m, (const double*)Q, W, alpha,
                        (const double*)A, (double*)out, info);
-  } else {
-    const size_t lds = (size_t)d * 16 * sizeof(float);
-    hipError_t e = hipFuncSetAttribute((const void*)rowmix_kernel<float>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(rowmix_kernel<float>, grid, dim3(256), lds, st, n, d, m, (const float*)Q, W, (float)alpha,
+  else
+    hipLaunchKernelGGL((rowmix_kernel<float, float>), grid, dim3(256), 0, st, n, d, m, (const float*)Q, W, alpha,
                        (const float*)A, (float*)out, info);
-  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rowmix_f64out(hipStream_t st, int64_t n, int d, int m, const void* Q, const double* W,
+                                double alpha, const void* A, double* out, bool in_f64) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  dim3 grid((unsigned)((n + 63) / 64), (unsigned)((m + 15) / 16));
+  if (in_f64)
+    hipLaunchKernelGGL((rowmix_kernel<double, double>), grid, dim3(256), 0, st, n, d, m, (const double*)Q, W, alpha,
+                       (const double*)A, out, nullptr);
+  else
+    hipLaunchKernelGGL((rowmix_kernel<float, double>), grid, dim3(256), 0, st, n, d, m, (const float*)Q, W, alpha,
+                       (const float*)A, out, nullptr);
+  return hipGetLastError();
+}
+
+__global__ void narrow_kernel(int64_t count, const double* __restrict__ in, float* __restrict__ out) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx < count) out[idx] = (float)in[idx];
+}
+
+hipError_t launch_narrow(hipStream_t st, int64_t count, const double* in, float* out) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(narrow_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count, in, out);
+  return hipGetLastError();
+}
+
+__global__ void wmix_kernel(int64_t count, const double* __restrict__ W, const double* __restrict__ Z,
+                            double inv_sigma2, const int32_t* __restrict__ info, double* __restrict__ out) {
+  if (info != nullptr && *info != 0) return;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx < count) out[idx] = W[idx] - Z[idx] * inv_sigma2;
+}
+
+hipError_t launch_wmix(hipStream_t st, int64_t count, const double* W, const double* Z, double sigma2,
+                       const int32_t* info, double* out) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(wmix_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count, W, Z, 1.0 / sigma2,
+                     info, out);
   return hipGetLastError();
 }
 

@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_version_and_status_strings():
     lib = L.lib()
-    assert lib.lr_version() >> 16 == 1
+    assert lib.lr_version() >> 16 == 2
     assert lib.lr_status_string(L.LR_ERR_NOT_POW2) == b"LR_ERR_NOT_POW2"
     assert lib.lr_status_string(99) == b"LR_UNKNOWN_STATUS"
 

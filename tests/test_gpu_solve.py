@@ -3,8 +3,14 @@ lr_lowrank_solve on its own, against the oracle.
 
 FP64 path: X and log|K~| within 1e-10 relative (the oracle and the GPU run the
 same algorithm in float64; differences are rounding order amplified by the
-conditioning of the d x d core). FP32 / BF16 paths: the error against the FP64
-oracle is measured and bounded by the stated per-path tolerances.
+conditioning of the d x d core). FP32 / BF16 paths are compared with the FP64
+oracle and with the oracle's precision model of that path: the sketch rounded
+as the path rounds it (float32 values; float32-evaluated kernel entries
+rounded to bfloat16 for BF16, gpu_common.kernel_matrix_f32), a
+float32 Householder QR (LAPACK, gpu_common.qr_fp32), then the float64 core
+and solve. The model's distance from the exact oracle measures how strongly
+the float64 method reacts to that rounding; the GPU's rounding differs in
+detail but not in size, so the bars are a fixed floor plus 4x that distance.
 """
 import math
 
@@ -14,7 +20,8 @@ import pytest
 import workloads as W
 from oracle import grad as og, lowrank as olr, sketch as osk
 
-from gpu_common import api, device, hyper, note, omega_pair, rel_max, to_dev, torch
+from gpu_common import (api, device, fl32, hyper, kernel_matrix_f32, note, omega_pair, qr_fp32, rel_max, to_dev,
+                        torch)
 
 pytestmark = pytest.mark.gpu
 
@@ -88,7 +95,12 @@ def test_gauss_fp64_largest_d():
     el = abs(sol.logdet.item() - ref["logdet"]) / abs(ref["logdet"])
     note(f"  X rel {ex:.2e} logdet rel {el:.2e}")
     assert int(sol.info.item()) == 0
-    assert ex <= 1e-9 and el <= 1e-10
+    assert ex <= 1e-10 and el <= 1e-10
+
+
+def _model_forward(x, w, om_np, A, y_model):
+    q, r = qr_fp32(y_model)
+    return olr.solve(q, r, om_np, w.sigma2, A)
 
 
 def test_srht_fp32_path_error_vs_fp64_oracle():
@@ -96,10 +108,13 @@ def test_srht_fp32_path_error_vs_fp64_oracle():
     w = W.small(W.WORKLOADS["C2"], 16384, d=128, leaf_rows=4096)
     x, A, om_np, _, Y, Q, R, sol = _forward(w, "f32", dev)
     ref = og.forward(x, w.kernel, w.ell, w.s, w.sigma2, om_np, A, w.leaf_rows)
+    mod = _model_forward(x, w, om_np, A, fl32(ref["Y"]))
     ex = rel_max(sol.X.cpu().numpy(), ref["X"])
     el = abs(sol.logdet.item() - ref["logdet"]) / abs(ref["logdet"])
-    note(f"  FP32 path: X rel {ex:.2e} logdet rel {el:.2e}")
-    assert ex <= 1e-3 and el <= 1e-6
+    mx = rel_max(mod["X"], ref["X"])
+    ml = abs(mod["logdet"] - ref["logdet"]) / abs(ref["logdet"])
+    note(f"  FP32 path: X rel {ex:.2e} logdet rel {el:.2e}; float32 model X {mx:.2e} logdet {ml:.2e}")
+    assert ex <= 1e-5 + 4.0 * mx and el <= 1e-8 + 4.0 * ml
 
 
 def test_bf16_path_error_vs_fp64_oracle():
@@ -108,11 +123,21 @@ def test_bf16_path_error_vs_fp64_oracle():
     x, A, om_np, _, Y, Q, R, sol = _forward(w, "bf16", dev)
     ref = og.forward(x, w.kernel, w.ell, w.s, w.sigma2, om_np, A, w.leaf_rows)
     refb = og.forward(x, w.kernel, w.ell, w.s, w.sigma2, om_np, A, w.leaf_rows, k_round="bf16")
+    # precision model: float32-evaluated kernel entries rounded to bf16
+    kb = osk.round_to_bf16(kernel_matrix_f32(w.kernel, x, x, w.ell, w.s))
+    mod = _model_forward(x, w, om_np, A, fl32(kb @ om_np["omega_t"].astype(np.float64).T))
     ex = rel_max(sol.X.cpu().numpy(), ref["X"])
     exb = rel_max(sol.X.cpu().numpy(), refb["X"])
     el = abs(sol.logdet.item() - ref["logdet"]) / abs(ref["logdet"])
-    note(f"  BF16 path: X rel vs fp64 {ex:.2e}, vs bf16-K oracle {exb:.2e}, logdet rel {el:.2e}")
+    elb = abs(sol.logdet.item() - refb["logdet"]) / abs(refb["logdet"])
+    mx = rel_max(mod["X"], refb["X"])
+    ml = abs(mod["logdet"] - refb["logdet"]) / abs(refb["logdet"])
+    note(f"  BF16 path: X rel vs fp64 {ex:.2e}, vs bf16-K oracle {exb:.2e} (float32 model {mx:.2e}); "
+         f"logdet rel {el:.2e}, vs bf16-K oracle {elb:.2e} (model {ml:.2e})")
+    # the bf16 rounding of K itself (G12 of the design notes: X moves by ~3e-2)
     assert ex <= 5e-2 and el <= 2e-4
+    # against the oracle that rounds K to bf16 as the kernel does
+    assert exb <= 1e-5 + 4.0 * mx and elb <= 1e-8 + 4.0 * ml
 
 
 def test_not_pd_reports_info_and_leaves_x():
@@ -138,23 +163,33 @@ def test_m_zero_computes_logdet_only():
     assert s0.X is None and abs(s0.logdet.item() - sol.logdet.item()) <= 1e-12 * abs(sol.logdet.item())
 
 
-def test_c3_full_bf16_pipeline_properties():
+def test_c3_full_bf16_stagewise():
+    """Full headline workload (n = 262144, d = 512, Matern-3/2, Gaussian Omega,
+    bf16 sketch): the oracle's core and Woodbury solve fed the GPU's own Q and R
+    (promoted) against the GPU's C, L, log-det and X. The GPU's F = Omega^T Q
+    sums float products in float32 for at most 512 rows (gamma_512 u32 of
+    |Omega|^T |Q|, see test_omega_t_q_product_against_oracle); C = F^{-1} R^T
+    and the Cholesky factor inherit that relative error times cond(F); X is
+    formed in float64 from Z = Q^T A summed exactly and rounded once to float32."""
     dev = device()
     w = W.WORKLOADS["C3"]
     x, A, om_np, om, Y, Q, R, sol = _forward(w, "bf16", dev)
     assert int(sol.info.item()) == 0
-    Xs = sol.X.double()
-    # K~ X = A checked through the factors: X = (A - Q Z)/s2 + Q S^{-1} Z
-    q = Q.double()
-    Ad = to_dev(A, torch.float64, dev)
-    z = q.T @ Ad
-    Lc = sol.L
-    w_ = torch.cholesky_solve(z, Lc)
-    xr = (Ad - q @ z) / w.sigma2 + q @ w_
-    err = ((Xs - xr).abs().max() / xr.abs().max()).item()
-    note(f"  C3 X vs factor-recomputation {err:.2e}, logdet {sol.logdet.item():.6e}")
-    assert err <= 1e-4
-    assert math.isfinite(sol.logdet.item())
+    q, r = Q.double().cpu().numpy(), R.cpu().numpy()
+    c = olr.core(q, r, om_np, w.sigma2)
+    assert c["info"] == 0
+    kf = float(np.linalg.cond(c["F"]))
+    tol_c = 10.0 * kf * 520 * 2.0 ** -24
+    eC = float(np.abs(sol.C.cpu().numpy() - c["C"]).max() / np.abs(c["C"]).max())
+    eL = float(np.abs(sol.L.cpu().numpy() - c["L"]).max() / np.abs(c["L"]).max())
+    ld = olr.logdet(c["L"], w.n, w.sigma2)
+    el = abs(sol.logdet.item() - ld) / abs(ld)
+    xr = olr.apply(q, c["L"], A, w.sigma2)
+    ex = rel_max(sol.X.double().cpu().numpy(), xr)
+    note(f"  C3 stage-wise: C {eC:.2e} L {eL:.2e} logdet {el:.2e} X {ex:.2e} (cond F {kf:.1f}, C/L bar {tol_c:.1e})")
+    assert eC <= tol_c and eL <= tol_c
+    assert el <= tol_c
+    assert ex <= 2.0 ** -24 + float(np.linalg.cond(c["S"])) * tol_c
 
 
 @pytest.mark.parametrize("prec", ["bf16", "f32"])
