@@ -162,12 +162,17 @@ lr_status lr_loglik(void *stream, int64_t n, int32_t prec, const void *y, const 
                     const double *logdet, const int32_t *info, double *out);
 
 /* ---------------------------------------------------------------- backward
- * Gradient with respect to theta = (log ell, log s, log sigma2), nu = 0 only.
- * (Not in the paper: the adjoint of steps 1-3 above.) For a symmetric G, the
- * derivative of the objective with respect to K~, d/dtheta = tr(G dK~/dtheta)
- * with, for Phi = F^{-1} and Y' = (dK_f/dlog ell) Omega,
+ * Gradient with respect to theta = (log ell, log s, log sigma2) for the
+ * forward's shift nu (a fixed parameter). (Not in the paper: the adjoint of
+ * steps 1-3 above.) For a symmetric G, the derivative of the objective with
+ * respect to K~, d/dtheta = tr(G dK~/dtheta) with, for Phi = F^{-1} and
+ * Y' = (dK_f/dlog ell) Omega,
  *   d/dlog ell    = 2 <G Q Phi, Y'> - <Phi^T (Q^T G Q) Phi, Omega^T Y'>,
- *   d/dlog s      = 2 tr(Q^T G Q C),   d/dlog sigma2 = sigma2 tr G.
+ *   d/dlog s      = 2 tr(Q^T G Q C),   d/dlog sigma2 = sigma2 tr G,
+ * and for nu > 0 (K~ = sigma2 I + Y W^{-1} Y^T - nu Q Q^T) the terms of the
+ * projector's derivative, -2 nu <(G Q - Q Q^T G Q) R^{-T}, Y''> for each
+ * derivative sketch Y'' (Y' for log ell, 2 (Y - nu Omega) for log s), plus the
+ * -2 nu Omega part of the log s sketch in the first two terms.
  *   mode 0 (log-likelihood -1/2 y^T K~^{-1} y - 1/2 log|K~|): G = (alpha alpha^T
  *          - K~^{-1})/2. A = y, the forward's right-hand side (device real
  *          n x 1, m must be 1); V and dA unused.
@@ -178,22 +183,26 @@ lr_status lr_loglik(void *stream, int64_t n, int32_t prec, const void *y, const 
  *   (Q^T A summed in float64 from exact products, S^{-1} by the Cholesky
  *   factor), and their Q-basis projections are taken as S^{-1} Q^T A, so the
  *   result does not depend on how closely a float32 Q satisfies Q^T Q = I.
- *   Q, C, L, Flu, piv   forward factors from lr_tsqr / lr_lowrank_solve.
+ *   Q, R, C, L, Flu, piv   forward factors from lr_tsqr / lr_lowrank_solve (R,
+ *           device double d x d upper triangular, is read only when nu > 0
+ *           and may be NULL otherwise).
+ *   sigma2 > 0, nu >= 0: the forward's nugget and shift.
  *   Yprime  device real n x d (dK_f/dlog ell) Omega from lr_sketch, or NULL to
  *           recompute it here (K tiles are recomputed, never stored).
  *   dtheta  device double[3]. */
 size_t lr_backward_workspace_bytes(int64_t n, int32_t D, int32_t d, int32_t m, int32_t prec);
 lr_status lr_backward(void *stream, int64_t n, int32_t D, const float *X, const lr_hyper *hyp,
-                      const lr_omega *omega, int32_t prec, const void *Q, const double *C,
-                      const double *L, const double *Flu, const int32_t *piv, double sigma2,
-                      int32_t mode, int32_t m, const void *A, const void *V, const void *Yprime,
-                      double *dtheta, void *dA, void *ws, size_t ws_bytes);
+                      const lr_omega *omega, int32_t prec, const void *Q, const double *R,
+                      const double *C, const double *L, const double *Flu, const int32_t *piv,
+                      double sigma2, double nu, int32_t mode, int32_t m, const void *A,
+                      const void *V, const void *Yprime, double *dtheta, void *dA, void *ws,
+                      size_t ws_bytes);
 
 /* Human-readable status name (static string). */
 const char *lr_status_string(int32_t status);
 
 /* ABI version: (major << 16) | minor. 2.0: lr_backward takes the forward's
- * right-hand side A instead of its solution. */
+ * right-hand side A instead of its solution, and R and the shift nu. */
 int32_t lr_version(void);
 
 #ifdef __cplusplus

@@ -51,7 +51,8 @@ _SIGS = {
     "lr_loglik": (c_i32, [c_vp, c_i64, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "lr_backward_workspace_bytes": (c_sz, [c_i64, c_i32, c_i32, c_i32, c_i32]),
     "lr_backward": (c_i32, [c_vp, c_i64, c_i32, c_vp, ctypes.POINTER(LrHyper), ctypes.POINTER(LrOmega), c_i32, c_vp,
-                            c_vp, c_vp, c_vp, c_vp, c_dbl, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz]),
+                            c_vp, c_vp, c_vp, c_vp, c_vp, c_dbl, c_dbl, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp,
+                            c_vp, c_sz]),
 }
 
 _lib = None

@@ -172,9 +172,10 @@ def loglik(y: torch.Tensor, alpha: torch.Tensor, logdet: torch.Tensor, info: tor
 
 def backward(X: torch.Tensor, hyper: Hyper, omega: Omega, prec: str, fac: SolveOut, Q: torch.Tensor, sigma2: float,
              mode: int, A: torch.Tensor, V: torch.Tensor | None = None, Yprime: torch.Tensor | None = None,
-             want_dA: bool = False):
+             want_dA: bool = False, R: torch.Tensor | None = None, nu: float = 0.0):
     """Gradient in (log ell, log s, log sigma2). ``A`` is the forward's
-    right-hand side (y for mode 0), ``V`` the cotangent Abar (mode 1)."""
+    right-hand side (y for mode 0), ``V`` the cotangent Abar (mode 1); with a
+    shift ``nu`` the forward's R factor is needed too."""
     n, D = X.shape
     dev = X.device
     _check_real(A, prec, "A")
@@ -186,8 +187,9 @@ def backward(X: torch.Tensor, hyper: Hyper, omega: Omega, prec: str, fac: SolveO
     lib = L.lib()
     ws = _Workspace(lib.lr_backward_workspace_bytes(n, D, omega.d, m, L.PRECS[prec]), dev)
     h, o = hyper.struct(), omega.struct()
-    L.check(lib.lr_backward(_stream(dev), n, D, _p(X), ctypes.byref(h), ctypes.byref(o), L.PRECS[prec], _p(Q),
-                            _p(fac.C), _p(fac.L), _p(fac.Flu), _p(fac.piv), float(sigma2), int(mode), m, _p(A), _p(V),
+    L.check(lib.lr_backward(_stream(dev), n, D, _p(X), ctypes.byref(h), ctypes.byref(o), L.PRECS[prec], _p(Q), _p(R),
+                            _p(fac.C), _p(fac.L), _p(fac.Flu), _p(fac.piv), float(sigma2), float(nu), int(mode), m,
+                            _p(A), _p(V),
                             _p(Yprime), _p(dtheta), _p(dA), ws.ptr, ws.nbytes), "lr_backward")
     return dtheta, dA
 

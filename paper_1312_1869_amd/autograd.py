@@ -44,7 +44,7 @@ class LowRankSolve(torch.autograd.Function):
         Ac = A.contiguous()
         fw = api.forward(X, hyper, omega, cfg.prec, sigma2, Ac, cfg.leaf_rows, nu=cfg.nu, want_yprime=cfg.fused)
         _check_info(fw.sol)
-        ctx.save_for_backward(X, fw.Q, Ac)
+        ctx.save_for_backward(X, fw.Q, Ac, fw.R)
         ctx.fac = fw.sol
         ctx.yprime = fw.Yprime
         ctx.omega, ctx.cfg, ctx.hyper, ctx.sigma2 = omega, cfg, hyper, sigma2
@@ -53,11 +53,10 @@ class LowRankSolve(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gX):
-        X, Q, A = ctx.saved_tensors
-        if ctx.cfg.nu != 0.0:
-            raise NotImplementedError("the adjoint is implemented for nu = 0")
+        X, Q, A, R = ctx.saved_tensors
         dtheta, dA = api.backward(X, ctx.hyper, ctx.omega, ctx.cfg.prec, ctx.fac, Q, ctx.sigma2, 1, A,
-                                  V=gX.contiguous().to(A.dtype), Yprime=ctx.yprime, want_dA=True)
+                                  V=gX.contiguous().to(A.dtype), Yprime=ctx.yprime, want_dA=True, R=R,
+                                  nu=ctx.cfg.nu)
         return dtheta.to(ctx.theta_device, ctx.theta_dtype), dA, None, None, None
 
 
@@ -71,7 +70,7 @@ class LowRankLogLik(torch.autograd.Function):
         fw = api.forward(X, hyper, omega, cfg.prec, sigma2, yc, cfg.leaf_rows, nu=cfg.nu, want_yprime=cfg.fused)
         _check_info(fw.sol)
         ll = api.loglik(yc, fw.sol.X, fw.sol.logdet, fw.sol.info, cfg.prec)
-        ctx.save_for_backward(X, fw.Q, yc)
+        ctx.save_for_backward(X, fw.Q, yc, fw.R)
         ctx.fac = fw.sol
         ctx.yprime = fw.Yprime
         ctx.omega, ctx.cfg, ctx.hyper, ctx.sigma2 = omega, cfg, hyper, sigma2
@@ -80,9 +79,7 @@ class LowRankLogLik(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
-        X, Q, yc = ctx.saved_tensors
-        if ctx.cfg.nu != 0.0:
-            raise NotImplementedError("the adjoint is implemented for nu = 0")
+        X, Q, yc, R = ctx.saved_tensors
         dtheta, _ = api.backward(X, ctx.hyper, ctx.omega, ctx.cfg.prec, ctx.fac, Q, ctx.sigma2, 0, yc,
-                                 Yprime=ctx.yprime)
+                                 Yprime=ctx.yprime, R=R, nu=ctx.cfg.nu)
         return (g.to(torch.float64) * dtheta).to(ctx.theta_device, ctx.theta_dtype), None, None, None, None

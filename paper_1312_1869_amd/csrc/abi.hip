@@ -219,7 +219,8 @@ lr_status woodbury_apply(hipStream_t st, int64_t n, int32_t d, int32_t m, int32_
 struct BackWs {
   size_t off_yp, off_sk, off_tn, off_za, off_wa, off_xa, off_zb, off_wb, off_xb, off_u64, off_b64, off_e, off_p,
       off_phi, off_sinv, off_t, off_g2, off_h, off_u, off_eu, off_ca, off_aa, off_xy, off_by, off_xbm, off_u1, off_u2,
-      off_eu1, off_eu2, off_cqb, total;
+      off_eu1, off_eu2, off_cqb, off_oo, off_v1, off_pta, off_oa, off_fa, off_oou, off_m1, off_m2, off_z1, off_z2,
+      off_ox, off_ob, off_fqx, off_fqb, off_oou2, total;
 };
 
 BackWs back_layout(int64_t n, int32_t D, int32_t d, int32_t m, int32_t prec) {
@@ -263,6 +264,22 @@ BackWs back_layout(int64_t n, int32_t D, int32_t d, int32_t m, int32_t prec) {
   take(w.off_eu1, dm8);
   take(w.off_eu2, dm8);
   take(w.off_cqb, dm8);
+  // shift terms
+  take(w.off_oo, dd8);
+  take(w.off_v1, (size_t)d * 8);
+  take(w.off_pta, (size_t)d * 8);
+  take(w.off_oa, (size_t)d * 8);
+  take(w.off_fa, (size_t)d * 8);
+  take(w.off_oou, (size_t)d * 8);
+  take(w.off_m1, dm8);
+  take(w.off_m2, dm8);
+  take(w.off_z1, dm8);
+  take(w.off_z2, dm8);
+  take(w.off_ox, dm8);
+  take(w.off_ob, dm8);
+  take(w.off_fqx, dm8);
+  take(w.off_fqb, dm8);
+  take(w.off_oou2, dm8);
   w.total = off;
   return w;
 }
@@ -402,9 +419,10 @@ size_t lr_backward_workspace_bytes(int64_t n, int32_t D, int32_t d, int32_t m, i
 }
 
 lr_status lr_backward(void* stream, int64_t n, int32_t D, const float* X, const lr_hyper* hyp, const lr_omega* omega,
-                      int32_t prec, const void* Q, const double* C, const double* L, const double* Flu,
-                      const int32_t* piv, double sigma2, int32_t mode, int32_t m, const void* A, const void* V,
-                      const void* Yprime, double* dtheta, void* dA, void* ws, size_t ws_bytes) {
+                      int32_t prec, const void* Q, const double* R, const double* C, const double* L,
+                      const double* Flu, const int32_t* piv, double sigma2, double nu, int32_t mode, int32_t m,
+                      const void* A, const void* V, const void* Yprime, double* dtheta, void* dA, void* ws,
+                      size_t ws_bytes) {
   if (!valid_prec(prec)) return LR_ERR_ARG;
   if (D < 1 || D > 15) return LR_ERR_SHAPE;
   if (omega == nullptr) return LR_ERR_ARG;
@@ -416,9 +434,9 @@ lr_status lr_backward(void* stream, int64_t n, int32_t D, const float* X, const 
   if (mode != 0 && mode != 1) return LR_ERR_ARG;
   if (mode == 0 && m != 1) return LR_ERR_SHAPE;
   if (mode == 1 && (m < 1 || m > 64)) return LR_ERR_SHAPE;
-  if (!is_fin(sigma2) || !(sigma2 > 0.0)) return LR_ERR_ARG;
+  if (!is_fin(sigma2) || !(sigma2 > 0.0) || !is_fin(nu) || nu < 0.0) return LR_ERR_ARG;
   if (X == nullptr || Q == nullptr || C == nullptr || L == nullptr || Flu == nullptr || piv == nullptr ||
-      A == nullptr || dtheta == nullptr || (mode == 1 && V == nullptr))
+      A == nullptr || dtheta == nullptr || (mode == 1 && V == nullptr) || (nu != 0.0 && R == nullptr))
     return LR_ERR_ARG;
   const BackWs w = back_layout(n, D, d, m, prec);
   if ((s = check_ws(w.total, ws, ws_bytes)) != LR_OK) return s;
@@ -454,6 +472,14 @@ lr_status lr_backward(void* stream, int64_t n, int32_t D, const float* X, const 
   b.E = E;
   b.C = C;
   b.dtheta = dtheta;
+  b.nu = nu;
+  const bool shifted = nu != 0.0;
+  double* OO = nullptr;  // Omega^T Omega (SRHT: the identity, not formed)
+  if (shifted && omega->kind == LR_OMEGA_GAUSS) {
+    OO = dptr(w.off_oo);
+    LR_HIP(launch_gemm_tn(st, n, d, d, om, om, oscale * oscale, OO, tn, true));
+  }
+  b.OO = OO;
   double* za = dptr(w.off_za);
   double* wa = dptr(w.off_wa);
   double* xa = dptr(w.off_xa);
@@ -491,6 +517,25 @@ lr_status lr_backward(void* stream, int64_t n, int32_t D, const float* X, const 
     b.P = P;
     b.G2 = G2;
     b.Sinv = Sinv;
+    if (shifted) {
+      double* v1 = dptr(w.off_v1);
+      double* Pta = dptr(w.off_pta);
+      double* oa = dptr(w.off_oa);
+      double* Fa = dptr(w.off_fa);
+      LR_HIP(launch_trsm_upper(st, d, 1, R, wa, v1, 1));
+      LR_HIP(launch_gemm_dd(st, d, 1, d, 1.0, P, d, true, wa, 1, false, 0.0, Pta, 1));
+      LR_HIP(launch_gemm_tn(st, n, d, 1, om, uo, oscale, oa, tn, true));
+      LR_HIP(launch_lu_apply(st, d, 1, Flu, piv, wa, Fa, 1));
+      b.v1 = v1;
+      b.Pta = Pta;
+      b.oa = oa;
+      b.Fa = Fa;
+      if (OO != nullptr) {
+        double* OOu = dptr(w.off_oou);
+        LR_HIP(launch_gemm_dd(st, d, 1, d, 1.0, OO, d, false, u, 1, false, 0.0, OOu, 1));
+        b.OOu = OOu;
+      }
+    }
   } else {
     double* zb = dptr(w.off_zb);
     double* wb = dptr(w.off_wb);
@@ -525,6 +570,42 @@ lr_status lr_backward(void* stream, int64_t n, int32_t D, const float* X, const 
     b.XY = XY;
     b.BY = BY;
     b.XB = XB;
+    if (shifted) {
+      double* P = dptr(w.off_p);
+      double* M1 = dptr(w.off_m1);
+      double* M2 = dptr(w.off_m2);
+      double* Z1 = dptr(w.off_z1);
+      double* Z2 = dptr(w.off_z2);
+      double* OX = dptr(w.off_ox);
+      double* OB = dptr(w.off_ob);
+      double* FQX = dptr(w.off_fqx);
+      double* FQB = dptr(w.off_fqb);
+      const size_t mdb = (size_t)m * d * sizeof(double);
+      LR_HIP(launch_gemm_tn(st, n, d, d, qo, ypo, 1.0, P, tn, true));
+      LR_HIP(hipMemcpyAsync(M1, XY, mdb, hipMemcpyDeviceToDevice, st));
+      LR_HIP(hipMemcpyAsync(M2, BY, mdb, hipMemcpyDeviceToDevice, st));
+      LR_HIP(launch_gemm_dd(st, m, d, d, -1.0, wa, m, true, P, d, false, 1.0, M1, d));
+      LR_HIP(launch_gemm_dd(st, m, d, d, -1.0, wb, m, true, P, d, false, 1.0, M2, d));
+      LR_HIP(launch_trsm_upper(st, d, m, R, wb, Z1, m));
+      LR_HIP(launch_trsm_upper(st, d, m, R, wa, Z2, m));
+      LR_HIP(launch_gemm_tn(st, n, d, m, om, uo, oscale, OX, tn, true));
+      LR_HIP(launch_gemm_tn(st, n, d, m, om, bo, oscale, OB, tn, true));
+      LR_HIP(launch_lu_apply(st, d, m, Flu, piv, wa, FQX, m));
+      LR_HIP(launch_lu_apply(st, d, m, Flu, piv, wb, FQB, m));
+      b.M1 = M1;
+      b.M2 = M2;
+      b.Z1 = Z1;
+      b.Z2 = Z2;
+      b.OX = OX;
+      b.OB = OB;
+      b.FQX = FQX;
+      b.FQB = FQB;
+      if (OO != nullptr) {
+        double* OOU2 = dptr(w.off_oou2);
+        LR_HIP(launch_gemm_dd(st, d, m, d, 1.0, OO, d, false, U2, m, false, 0.0, OOU2, m));
+        b.OOU2 = OOU2;
+      }
+    }
   }
   LR_HIP(launch_backward_scalars(st, b));
   return LR_OK;

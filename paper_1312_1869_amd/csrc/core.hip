@@ -481,6 +481,14 @@ hipError_t launch_core_apply(hipStream_t st, int d, int m, const double* L, cons
 //     d/dlog ell    = -(<U2, XY^T> + <U1, BY^T>) + (<U1, E U2> + <U2, E U1>) / 2
 //     d/dlog s      = -2 <QX, C QB>
 //     d/dlog sigma2 = -sigma2 tr(X^T B)
+//   with a shift nu (v1 = R^{-1} a, o = Omega^T alpha, OO = Omega^T Omega):
+//     log-likelihood: d/dlog ell += -nu (h - P^T a).v1
+//                     d/dlog s   += -2 nu (u.o - tr S^{-1}) + nu (u.OO u - <G2, OO>)
+//                                   + 2 nu^2 (o - F a).v1
+//     solve (M1 = XY - QX^T P, M2 = BY - QB^T P, Z1 = R^{-1} QB, Z2 = R^{-1} QX):
+//                     d/dlog ell += nu (<M1^T, Z1> + <M2^T, Z2>)
+//                     d/dlog s   += 2 nu (<U2, Omega^T X> + <U1, Omega^T B>) - 2 nu <U1, OO U2>
+//                                   - 2 nu^2 (<Omega^T X - F QX, Z1> + <Omega^T B - F QB, Z2>)
 __global__ __launch_bounds__(kCoreThreads) void backward_scalars_kernel(BackwardScalars b) {
   __shared__ double red[kCoreWaves];
   const int t = threadIdx.x;
@@ -507,10 +515,30 @@ __global__ __launch_bounds__(kCoreThreads) void backward_scalars_kernel(Backward
     const double tp = block_sum(p_tp, red);
     const double ge = block_sum(p_ge, red);
     const double sc = block_sum(p_sc, red);
+    double x_ell = 0.0, x_s = 0.0;
+    if (b.nu != 0.0) {
+      double q_hv = 0.0, q_uo = 0.0, q_uu = 0.0, q_ov = 0.0, q_g = 0.0;
+      for (int i = t; i < d; i += kCoreThreads) {
+        q_hv += (b.h[i] - b.Pta[i]) * b.v1[i];
+        q_uo += b.u[i] * b.oa[i];
+        q_uu += b.u[i] * (b.OOu != nullptr ? b.OOu[i] : b.u[i]);
+        q_ov += (b.oa[i] - b.Fa[i]) * b.v1[i];
+        if (b.OO == nullptr) q_g += b.G2[(int64_t)i * d + i];
+      }
+      if (b.OO != nullptr)
+        for (int64_t e = t; e < dd; e += kCoreThreads) q_g += b.G2[e] * b.OO[e];
+      const double hv = block_sum(q_hv, red);
+      const double uo = block_sum(q_uo, red);
+      const double uu = block_sum(q_uu, red);
+      const double ov = block_sum(q_ov, red);
+      const double g2oo = block_sum(q_g, red);
+      x_ell = -b.nu * hv;
+      x_s = -2.0 * b.nu * (uo - trs) + b.nu * (uu - g2oo) + 2.0 * b.nu * b.nu * ov;
+    }
     if (t == 0) {
       const double t2 = 0.5 * (uEu - ge);
-      b.dtheta[0] = uh - tp - t2;
-      b.dtheta[1] = aCa - sc;
+      b.dtheta[0] = uh - tp - t2 + x_ell;
+      b.dtheta[1] = aCa - sc + x_s;
       b.dtheta[2] = b.sigma2 * 0.5 * (b.aa[0] - ((double)(b.n - d) / b.sigma2 + trs));
     }
   } else {
@@ -528,9 +556,26 @@ __global__ __launch_bounds__(kCoreThreads) void backward_scalars_kernel(Backward
     const double t2 = block_sum(p_t2, red);
     const double mc = block_sum(p_mc, red);
     const double xb = block_sum(p_xb, red);
+    double x_ell = 0.0, x_s = 0.0;
+    if (b.nu != 0.0) {
+      double q_mz = 0.0, q_uo = 0.0, q_uu = 0.0, q_oz = 0.0;
+      for (int64_t e = t; e < dm; e += kCoreThreads) {
+        const int i = (int)(e / m), c = (int)(e % m);
+        q_mz += b.M1[(int64_t)c * d + i] * b.Z1[e] + b.M2[(int64_t)c * d + i] * b.Z2[e];
+        q_uo += b.U2[e] * b.OX[e] + b.U1[e] * b.OB[e];
+        q_uu += b.U1[e] * (b.OOU2 != nullptr ? b.OOU2[e] : b.U2[e]);
+        q_oz += (b.OX[e] - b.FQX[e]) * b.Z1[e] + (b.OB[e] - b.FQB[e]) * b.Z2[e];
+      }
+      const double mz = block_sum(q_mz, red);
+      const double uo = block_sum(q_uo, red);
+      const double uu = block_sum(q_uu, red);
+      const double oz = block_sum(q_oz, red);
+      x_ell = b.nu * mz;
+      x_s = 2.0 * b.nu * uo - 2.0 * b.nu * uu - 2.0 * b.nu * b.nu * oz;
+    }
     if (t == 0) {
-      b.dtheta[0] = -t1 + 0.5 * t2;
-      b.dtheta[1] = -2.0 * mc;
+      b.dtheta[0] = -t1 + 0.5 * t2 + x_ell;
+      b.dtheta[1] = -2.0 * mc + x_s;
       b.dtheta[2] = -b.sigma2 * xb;
     }
   }

@@ -16,7 +16,9 @@
 //      Cholesky: X <- L^{-T} L^{-1} X for a lower factor L (S = L L^T).
 //    Right-hand sides come from X itself, from another d x nrhs matrix, from
 //    the rows of a matrix (column c is row c of src: F^{-1} R^T), or from the
-//    identity (an inverse).
+//    identity (an inverse). A third mode applies only an upper triangle
+//    (R^{-1} B for the TSQR factor).
+//  * lu_apply: F B from the getrf factors of F.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -207,7 +209,9 @@ __device__ void trsm_sweep(const double* __restrict__ Fm, int d, double* xs, dou
 
 // src_kind: 0 = X itself, 1 = column c is row c of src (src d x d), 2 = identity,
 // 3 = src (d x nrhs, leading dimension ldx).
-template <bool CHOL>
+// MODE: 0 = LU (getrf factors, piv may be NULL for none), 1 = Cholesky,
+// 2 = upper triangle of Fm only (X <- U^{-1} B, e.g. U = R).
+template <int MODE>
 __global__ __launch_bounds__(256) void trsm_cols_kernel(int d, int nrhs, const double* __restrict__ Fm,
                                                         const int32_t* __restrict__ piv, int src_kind,
                                                         const double* __restrict__ src, double* X, int ldx,
@@ -230,7 +234,8 @@ __global__ __launch_bounds__(256) void trsm_cols_kernel(int d, int nrhs, const d
     xs[e] = v;
   }
   __syncthreads();
-  if (!CHOL) {
+  constexpr bool CHOL = MODE == 1;
+  if (MODE == 0 && piv != nullptr) {
     // row exchanges in factorisation order, one thread per column
     if (t < kTrNc) {
       for (int k = 0; k < d; ++k) {
@@ -244,7 +249,7 @@ __global__ __launch_bounds__(256) void trsm_cols_kernel(int d, int nrhs, const d
     }
     __syncthreads();
   }
-  trsm_sweep<CHOL, false>(Fm, d, xs, tile);
+  if (MODE != 2) trsm_sweep<CHOL, false>(Fm, d, xs, tile);
   trsm_sweep<CHOL, true>(Fm, d, xs, tile);
   for (int e = t; e < d * kTrNc; e += 256) {
     const int i = e / kTrNc, c = e % kTrNc;
@@ -258,10 +263,65 @@ hipError_t launch_trsm_cols(hipStream_t st, bool chol, int d, int nrhs, const do
   if (d < 1 || d > kTrMaxD) return hipErrorInvalidValue;
   dim3 grid((unsigned)((nrhs + kTrNc - 1) / kTrNc));
   if (chol)
-    hipLaunchKernelGGL(trsm_cols_kernel<true>, grid, dim3(256), 0, st, d, nrhs, Fm, piv, src_kind, src, X, ldx, info);
+    hipLaunchKernelGGL(trsm_cols_kernel<1>, grid, dim3(256), 0, st, d, nrhs, Fm, piv, src_kind, src, X, ldx, info);
   else
-    hipLaunchKernelGGL(trsm_cols_kernel<false>, grid, dim3(256), 0, st, d, nrhs, Fm, piv, src_kind, src, X, ldx,
-                       info);
+    hipLaunchKernelGGL(trsm_cols_kernel<0>, grid, dim3(256), 0, st, d, nrhs, Fm, piv, src_kind, src, X, ldx, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm_upper(hipStream_t st, int d, int nrhs, const double* U, const double* src, double* X,
+                             int ldx) {
+  if (nrhs <= 0) return hipSuccess;
+  if (d < 1 || d > kTrMaxD) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((nrhs + kTrNc - 1) / kTrNc));
+  hipLaunchKernelGGL(trsm_cols_kernel<2>, grid, dim3(256), 0, st, d, nrhs, U, nullptr, 3, src, X, ldx, nullptr);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ lu_apply
+
+// out = F B for F = P^T L U given by its getrf factors (B, out d x nrhs with
+// leading dimension ld; one workgroup per column, the column in LDS):
+// t = U b, t = L t (unit lower), then the row exchanges undone last to first.
+__global__ __launch_bounds__(256) void lu_apply_kernel(int d, int nrhs, const double* __restrict__ Flu,
+                                                       const int32_t* __restrict__ piv, const double* __restrict__ B,
+                                                       double* __restrict__ out, int ld) {
+  __shared__ double b[kTrMaxD];
+  __shared__ double t[kTrMaxD];
+  const int c = blockIdx.x;
+  for (int i = threadIdx.x; i < d; i += 256) b[i] = B[(int64_t)i * ld + c];
+  __syncthreads();
+  for (int i = threadIdx.x; i < d; i += 256) {  // (U b)_i = sum_{k >= i} U[i][k] b_k
+    double s = 0.0;
+    for (int k = i; k < d; ++k) s = fma(Flu[(int64_t)i * d + k], b[k], s);
+    t[i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < d; i += 256) {  // (L t)_i = t_i + sum_{k < i} L[i][k] t_k
+    double s = t[i];
+    for (int k = 0; k < i; ++k) s = fma(Flu[(int64_t)i * d + k], t[k], s);
+    b[i] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = d - 1; k >= 0; --k) {
+      const int p = piv[k];
+      if (p != k && p >= 0 && p < d) {
+        const double x = b[k];
+        b[k] = b[p];
+        b[p] = x;
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < d; i += 256) out[(int64_t)i * ld + c] = b[i];
+}
+
+hipError_t launch_lu_apply(hipStream_t st, int d, int nrhs, const double* Flu, const int32_t* piv, const double* B,
+                           double* out, int ld) {
+  if (nrhs <= 0) return hipSuccess;
+  if (d < 1 || d > kTrMaxD) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(lu_apply_kernel, dim3((unsigned)nrhs), dim3(256), 0, st, d, nrhs, Flu, piv, B, out, ld);
   return hipGetLastError();
 }
 

@@ -96,6 +96,23 @@ struct BackwardScalars {
   const double* XY;     // X^T Y' (m x d)
   const double* BY;     // B^T Y' (m x d)
   const double* XB;     // X^T B (m x m)
+  // shift nu != 0 (Y = (K_f + nu I) Omega): projector and Omega terms
+  double nu;
+  const double* OO;     // Omega^T Omega (d x d), NULL for SRHT (= I)
+  const double* v1;     // mode 0: R^{-1} a (d)
+  const double* Pta;    // mode 0: P^T a (d)
+  const double* oa;     // mode 0: Omega^T alpha (d)
+  const double* Fa;     // mode 0: F a (d)
+  const double* OOu;    // mode 0: Omega^T Omega u (d), NULL for SRHT
+  const double* M1;     // mode 1: XY - QX^T P (m x d)
+  const double* M2;     // mode 1: BY - QB^T P (m x d)
+  const double* Z1;     // mode 1: R^{-1} QB (d x m)
+  const double* Z2;     // mode 1: R^{-1} QX (d x m)
+  const double* OX;     // mode 1: Omega^T X (d x m)
+  const double* OB;     // mode 1: Omega^T B (d x m)
+  const double* FQX;    // mode 1: F QX (d x m)
+  const double* FQB;    // mode 1: F QB (d x m)
+  const double* OOU2;   // mode 1: Omega^T Omega U2 (d x m), NULL for SRHT
   double* dtheta;
 };
 hipError_t launch_backward_scalars(hipStream_t st, const BackwardScalars& b);
@@ -110,6 +127,12 @@ hipError_t launch_gemm_dd(hipStream_t st, int M, int N, int K, double alpha, con
 // Skipped when *info != 0.
 hipError_t launch_trsm_cols(hipStream_t st, bool chol, int d, int nrhs, const double* Fm, const int32_t* piv,
                             int src_kind, const double* src, double* X, int ldx, const int32_t* info);
+// dense.hip: X <- U^{-1} src for the upper triangle of U (d x d), nrhs columns.
+hipError_t launch_trsm_upper(hipStream_t st, int d, int nrhs, const double* U, const double* src, double* X,
+                             int ldx);
+// dense.hip: out = F B, F given by its getrf factors (B, out d x nrhs, leading dimension ld).
+hipError_t launch_lu_apply(hipStream_t st, int d, int nrhs, const double* Flu, const int32_t* piv, const double* B,
+                           double* out, int ld);
 hipError_t launch_identity(hipStream_t st, double* X, int d);
 
 }  // namespace lr

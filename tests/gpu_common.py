@@ -71,26 +71,12 @@ def qr_fp32(y):
     return q.astype(np.float64) * sg[None, :], r.astype(np.float64) * sg[:, None]
 
 
-def kernel_matrix_f32(kind: str, xa, xb, ell: float, s: float):
-    """Precision model of a float32 kernel evaluation: the squared distance in
-    difference form and the kernel formula (SE s^2 exp(-r^2 / (2 ell^2)),
-    Matern-3/2 s^2 (1 + u) exp(-u), u = sqrt(3) r / ell) in float32
-    arithmetic. Used with a bf16 rounding of the result to model the bf16
-    sketch, whose kernel entries are float32 values rounded to bf16: an entry
-    within a few float32 ulps of a bf16 rounding midpoint may round either way
-    depending on the evaluation, and the oracle's float64 evaluation picks one
-    side."""
-    xa = np.asarray(xa, dtype=np.float32)
-    xb = np.asarray(xb, dtype=np.float32)
-    r2 = np.zeros((xa.shape[0], xb.shape[0]), dtype=np.float32)
-    for t in range(xa.shape[1]):
-        diff = xa[:, t][:, None] - xb[:, t][None, :]
-        r2 += diff * diff
-    s2 = np.float32(s * s)
-    if kind == "se":
-        return (s2 * np.exp(-r2 / np.float32(2.0 * ell * ell))).astype(np.float64)
-    u = np.float32(math.sqrt(3.0) / ell) * np.sqrt(r2)
-    return (s2 * (np.float32(1.0) + u) * np.exp(-u)).astype(np.float64)
+def qr_fp64(y):
+    """LAPACK's float64 Householder QR (numpy) with diag(R) >= 0: a fast
+    float64 QR for sampling how the method reacts to perturbed sketches."""
+    q, r = np.linalg.qr(np.asarray(y, dtype=np.float64))
+    sg = np.where(np.diag(r) < 0, -1.0, 1.0)
+    return q * sg[None, :], r * sg[:, None]
 
 
 def fl32(a):

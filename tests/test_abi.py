@@ -122,10 +122,12 @@ def test_solve_and_backward_validation():
     assert s(wsb=8) == L.LR_ERR_WORKSPACE
     assert s(prec=L.LR_PREC_BF16) == L.LR_ERR_UNSUPPORTED
     hyp = _hyper()
-    b = lambda mode=0, m=1, sigma2=1e-3: lib.lr_backward(None, 1024, 2, FAKE, ctypes.byref(hyp), ctypes.byref(om),
-                                                         L.LR_PREC_F32, FAKE, FAKE, FAKE, FAKE, FAKE, sigma2, mode, m,
-                                                         FAKE, FAKE, None, FAKE, None, ws, 1 << 40)
+    b = lambda mode=0, m=1, sigma2=1e-3, nu=0.0, R=FAKE: lib.lr_backward(
+        None, 1024, 2, FAKE, ctypes.byref(hyp), ctypes.byref(om), L.LR_PREC_F32, FAKE, R, FAKE, FAKE, FAKE, FAKE,
+        sigma2, nu, mode, m, FAKE, FAKE, None, FAKE, None, ws, 1 << 40)
     assert b(mode=2) == L.LR_ERR_ARG
     assert b(mode=0, m=2) == L.LR_ERR_SHAPE
     assert b(sigma2=float("nan")) == L.LR_ERR_ARG
+    assert b(nu=-1e-3) == L.LR_ERR_ARG
+    assert b(nu=1e-4, R=None) == L.LR_ERR_ARG     # a shift needs R
     assert lib.lr_loglik(None, 0, L.LR_PREC_F32, FAKE, FAKE, FAKE, None, FAKE) == L.LR_ERR_SHAPE

@@ -4,13 +4,14 @@ lr_lowrank_solve on its own, against the oracle.
 FP64 path: X and log|K~| within 1e-10 relative (the oracle and the GPU run the
 same algorithm in float64; differences are rounding order amplified by the
 conditioning of the d x d core). FP32 / BF16 paths are compared with the FP64
-oracle and with the oracle's precision model of that path: the sketch rounded
-as the path rounds it (float32 values; float32-evaluated kernel entries
-rounded to bfloat16 for BF16, gpu_common.kernel_matrix_f32), a
-float32 Householder QR (LAPACK, gpu_common.qr_fp32), then the float64 core
-and solve. The model's distance from the exact oracle measures how strongly
-the float64 method reacts to that rounding; the GPU's rounding differs in
-detail but not in size, so the bars are a fixed floor plus 4x that distance.
+oracle and with the oracle's precision model of that path: the GPU's own
+sketch (a stage input: its float32 values, and for BF16 its bf16-rounded
+float32 kernel entries, whose rounding may fall on either side of a bf16
+midpoint from the oracle's float64 evaluation), a float32 Householder QR
+(LAPACK, gpu_common.qr_fp32), then the float64 core and solve. The model's
+distance from the exact oracle measures how strongly the float64 method
+reacts to that rounding; the GPU's float32 QR differs from LAPACK's in detail
+but not in size, so the bars are a fixed floor plus 4x that distance.
 """
 import math
 
@@ -20,8 +21,7 @@ import pytest
 import workloads as W
 from oracle import grad as og, lowrank as olr, sketch as osk
 
-from gpu_common import (api, device, fl32, hyper, kernel_matrix_f32, note, omega_pair, qr_fp32, rel_max, to_dev,
-                        torch)
+from gpu_common import api, device, hyper, note, omega_pair, qr_fp32, rel_max, to_dev, torch
 
 pytestmark = pytest.mark.gpu
 
@@ -108,7 +108,7 @@ def test_srht_fp32_path_error_vs_fp64_oracle():
     w = W.small(W.WORKLOADS["C2"], 16384, d=128, leaf_rows=4096)
     x, A, om_np, _, Y, Q, R, sol = _forward(w, "f32", dev)
     ref = og.forward(x, w.kernel, w.ell, w.s, w.sigma2, om_np, A, w.leaf_rows)
-    mod = _model_forward(x, w, om_np, A, fl32(ref["Y"]))
+    mod = _model_forward(x, w, om_np, A, Y.double().cpu().numpy())
     ex = rel_max(sol.X.cpu().numpy(), ref["X"])
     el = abs(sol.logdet.item() - ref["logdet"]) / abs(ref["logdet"])
     mx = rel_max(mod["X"], ref["X"])
@@ -123,9 +123,9 @@ def test_bf16_path_error_vs_fp64_oracle():
     x, A, om_np, _, Y, Q, R, sol = _forward(w, "bf16", dev)
     ref = og.forward(x, w.kernel, w.ell, w.s, w.sigma2, om_np, A, w.leaf_rows)
     refb = og.forward(x, w.kernel, w.ell, w.s, w.sigma2, om_np, A, w.leaf_rows, k_round="bf16")
-    # precision model: float32-evaluated kernel entries rounded to bf16
-    kb = osk.round_to_bf16(kernel_matrix_f32(w.kernel, x, x, w.ell, w.s))
-    mod = _model_forward(x, w, om_np, A, fl32(kb @ om_np["omega_t"].astype(np.float64).T))
+    # precision model: the GPU's sketch (float32-evaluated kernel entries
+    # rounded to bf16, float32 sums), LAPACK's float32 QR, float64 core
+    mod = _model_forward(x, w, om_np, A, Y.double().cpu().numpy())
     ex = rel_max(sol.X.cpu().numpy(), ref["X"])
     exb = rel_max(sol.X.cpu().numpy(), refb["X"])
     el = abs(sol.logdet.item() - ref["logdet"]) / abs(ref["logdet"])
