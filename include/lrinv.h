@@ -56,7 +56,8 @@ typedef enum {
   LR_ERR_NOT_POW2 = 3,    /* SRHT Omega with n not a power of two */
   LR_ERR_WORKSPACE = 4,   /* workspace smaller than required or misaligned */
   LR_ERR_HIP = 5,         /* a HIP runtime call or kernel launch failed */
-  LR_ERR_UNSUPPORTED = 6  /* valid but unsupported combination */
+  LR_ERR_UNSUPPORTED = 6, /* valid but unsupported combination */
+  LR_ERR_SCRATCH_LIMIT = 7 /* larger than the static scratch of lr_sketch_noalloc */
 } lr_status;
 
 typedef enum { LR_KERNEL_SE = 0, LR_KERNEL_MATERN32 = 1 } lr_kernel;
@@ -116,6 +117,24 @@ size_t lr_sketch_workspace_bytes(int64_t n, int32_t D, int32_t d, int32_t prec);
 lr_status lr_sketch(void *stream, int64_t n, int32_t D, const float *X, const lr_hyper *hyp,
                     const lr_omega *omega, double nu, int32_t prec, void *Y, void *Yprime,
                     void *ws, size_t ws_bytes);
+
+/* ---------------------------------------------------------------- sketch, no allocation
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): lr_sketch
+ * with its workspace (the prescaled points) in a static device array of
+ * LR_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds until the
+ * process ends. Nothing is allocated or freed: the caller passes X, Y and
+ * Yprime as for lr_sketch.
+ *   Returns LR_ERR_SCRATCH_LIMIT when lr_sketch_workspace_bytes(n, D, d, prec)
+ *   exceeds the array (about (n + 128) x 16 bytes for D <= 3 in float32:
+ *   n <= 2,097,024; half that in float64), and LR_ERR_UNSUPPORTED for the bf16
+ *   Gaussian sketch with D <= 3, whose operand copy of Omega (2 n d bytes) does
+ *   not fit a static array. Every call on one GPU uses that GPU's array and
+ *   leaves its contents behind; calls that overlap on one GPU (two streams,
+ *   two threads) race on it and must be serialised by the caller. */
+#define LR_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+lr_status lr_sketch_noalloc(void *stream, int64_t n, int32_t D, const float *X, const lr_hyper *hyp,
+                            const lr_omega *omega, double nu, int32_t prec, void *Y, void *Yprime);
 
 /* ---------------------------------------------------------------- tsqr
  * Binary-tree blocked QR of the n x d matrix Y (Sec. 3.3, Eq. 1-4).

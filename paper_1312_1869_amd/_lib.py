@@ -10,7 +10,9 @@ import os
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblrinv.so")
 
-LR_OK, LR_ERR_ARG, LR_ERR_SHAPE, LR_ERR_NOT_POW2, LR_ERR_WORKSPACE, LR_ERR_HIP, LR_ERR_UNSUPPORTED = range(7)
+(LR_OK, LR_ERR_ARG, LR_ERR_SHAPE, LR_ERR_NOT_POW2, LR_ERR_WORKSPACE, LR_ERR_HIP, LR_ERR_UNSUPPORTED,
+ LR_ERR_SCRATCH_LIMIT) = range(8)
+NOALLOC_SCRATCH_BYTES = 32 << 20
 LR_KERNEL_SE, LR_KERNEL_MATERN32 = 0, 1
 LR_OMEGA_SRHT, LR_OMEGA_GAUSS = 0, 1
 LR_PREC_F64, LR_PREC_F32, LR_PREC_BF16 = 0, 1, 2
@@ -43,6 +45,8 @@ _SIGS = {
     "lr_sketch_workspace_bytes": (c_sz, [c_i64, c_i32, c_i32, c_i32]),
     "lr_sketch": (c_i32, [c_vp, c_i64, c_i32, c_vp, ctypes.POINTER(LrHyper), ctypes.POINTER(LrOmega), c_dbl, c_i32,
                           c_vp, c_vp, c_vp, c_sz]),
+    "lr_sketch_noalloc": (c_i32, [c_vp, c_i64, c_i32, c_vp, ctypes.POINTER(LrHyper), ctypes.POINTER(LrOmega), c_dbl,
+                                  c_i32, c_vp, c_vp]),
     "lr_tsqr_workspace_bytes": (c_sz, [c_i64, c_i32, c_i32, c_i32]),
     "lr_tsqr": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_sz]),
     "lr_lowrank_solve_workspace_bytes": (c_sz, [c_i64, c_i32, c_i32, c_i32]),

@@ -30,6 +30,29 @@ int num_cu_current() {
   return g_num_cu[dev];
 }
 
+// Scratch of lr_sketch_noalloc: a file-scope device array (each GPU the
+// library runs on holds its own copy until the process ends). In host code
+// the name is only a host-side stand-in; the device address comes from
+// hipGetSymbolAddress, once per device, and is the only thing passed to
+// kernels.
+constexpr size_t kNoAllocBytes = LR_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char lr_scratch[kNoAllocBytes];
+void* g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+std::once_flag g_scratch_once[kMaxDevices];
+
+// Device address of this GPU's scratch array (nullptr on failure).
+void* scratch_current() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::call_once(g_scratch_once[dev], [dev]() {
+    void* ptr = nullptr;
+    g_scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(lr_scratch));
+    g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? ptr : nullptr;
+  });
+  return g_scratch_ptr[dev];
+}
+
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 bool is_fin(double x) { return isfinite(x) != 0; }
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
@@ -308,6 +331,7 @@ const char* lr_status_string(int32_t s) {
     case LR_ERR_WORKSPACE: return "LR_ERR_WORKSPACE";
     case LR_ERR_HIP: return "LR_ERR_HIP";
     case LR_ERR_UNSUPPORTED: return "LR_ERR_UNSUPPORTED";
+    case LR_ERR_SCRATCH_LIMIT: return "LR_ERR_SCRATCH_LIMIT";
     default: return "LR_UNKNOWN_STATUS";
   }
 }
@@ -340,6 +364,25 @@ lr_status lr_sketch(void* stream, int64_t n, int32_t D, const float* X, const lr
   if ((s = check_omega(omega, n, omega->d, prec)) != LR_OK) return s;
   if (!is_fin(nu) || nu < 0.0) return LR_ERR_ARG;
   if ((s = check_ws(sketch_ws(n, D, omega->d, prec), ws, ws_bytes)) != LR_OK) return s;
+  return sketch_impl(static_cast<hipStream_t>(stream), n, D, X, hyp, omega, nu, prec, Y, Yprime, ws);
+}
+
+lr_status lr_sketch_noalloc(void* stream, int64_t n, int32_t D, const float* X, const lr_hyper* hyp,
+                            const lr_omega* omega, double nu, int32_t prec, void* Y, void* Yprime) {
+  if (!valid_prec(prec)) return LR_ERR_ARG;
+  if (D < 1 || D > 15) return LR_ERR_SHAPE;
+  if (omega == nullptr) return LR_ERR_ARG;
+  lr_status s = check_sizes(n, omega->d);
+  if (s != LR_OK) return s;
+  if (X == nullptr || (Y == nullptr && Yprime == nullptr)) return LR_ERR_ARG;
+  if ((s = check_hyper(hyp)) != LR_OK) return s;
+  if ((s = check_omega(omega, n, omega->d, prec)) != LR_OK) return s;
+  if (!is_fin(nu) || nu < 0.0) return LR_ERR_ARG;
+  // the bf16 matrix-core sketch with D <= 3 reads a 2 n d byte operand copy of Omega
+  if (prec == LR_PREC_BF16 && D <= 3 && omega->kind == LR_OMEGA_GAUSS) return LR_ERR_UNSUPPORTED;
+  if (sketch_ws(n, D, omega->d, prec) > kNoAllocBytes) return LR_ERR_SCRATCH_LIMIT;
+  void* ws = scratch_current();
+  if (ws == nullptr) return LR_ERR_HIP;
   return sketch_impl(static_cast<hipStream_t>(stream), n, D, X, hyp, omega, nu, prec, Y, Yprime, ws);
 }
 
