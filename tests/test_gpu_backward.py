@@ -332,7 +332,15 @@ def test_c4_full_fp64_gradient():
     g = r["g"]
     g_st = og.grad_loglik(x, w.kernel, w.ell, w.s, w.sigma2, r["om"], r["Q"], r["core"], yv, yprime=r["Yp"])
     e_st = _rel(g, g_st)
-    sbar = _loglik_stage_bar(r, yv, w.sigma2, g_st, 0.0)
+    keys = ["grad_logell", "grad_logs", "grad_logsigma2"]
+    g_ref = np.array([gold[k] for k in keys])
+    g_lap = np.array([gold[k + "_f64lapack"] for k in keys])
+    # with trailing singular values at ~1e-15 the factors satisfy the identities
+    # the formulas rely on (Q^T Q = I, C = sym(F^-1 R^T)) only to round-off
+    # amplified by that conditioning, so two evaluations of the formulas on the
+    # same factors may differ by as much as two float64 QRs of the same sketch
+    # move the oracle's gradient (the stored LAPACK-QR run)
+    sbar = np.maximum(_loglik_stage_bar(r, yv, w.sigma2, g_st, 0.0), 4.0 * np.abs(g_lap - g_ref))
     om_np, om = omega_pair(w, "f64", dev)
     X = to_dev(x, torch.float32, dev)
     y = to_dev(yv, torch.float64, dev).reshape(-1, 1)
@@ -355,8 +363,6 @@ def test_c4_full_fp64_gradient():
         d1 = (ll_at(th0 + h * e) - ll_at(th0 - h * e)) / (2 * h)
         d2 = (ll_at(th0 + 0.5 * h * e) - ll_at(th0 - 0.5 * h * e)) / h
         fd[k] = (4 * d2 - d1) / 3
-    keys = ["grad_logell", "grad_logs", "grad_logsigma2"]
-    g_ref = np.array([gold[k] for k in keys])
     beta, orth = _qr_backward_errors(r["Y"], r["Q"], r["R"])
     g_s = [_oracle_loglik_grad(x, w, r["om"], yv, _perturbed(r["Y"], beta, k), r["Yp"], lapack=True)[0]
            for k in range(8)]
