@@ -32,6 +32,9 @@ PEAKS = {  # MI355X published dense peaks
     "fp32_tflops": 157.3,
     "fp64_tflops": 78.6,
     "hbm_gbs": 8000.0,
+    # plain FP32 vector adds without packed math (the build disables packed
+    # FP32): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+    "fp32_add_tops": 256 * 4 * 16 * 2.4e9 / 1e12,
 }
 METRIC = "K⁻¹A low-rank solve s & TFLOP/s, FP32/BF16 vs FP64 GPU, n=262144 d=512"
 
@@ -97,6 +100,15 @@ def cpu_baseline(w, x, om_np, sketch_flops: float, budget_s: float = 12.0) -> di
     from oracle import sketch as osk
 
     threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     rows_done, t0 = 0, time.perf_counter()
     rng = np.random.default_rng(11)
     block = 64
@@ -108,8 +120,73 @@ def cpu_baseline(w, x, om_np, sketch_flops: float, budget_s: float = 12.0) -> di
     flops = sketch_flops / w.n * rows_done
     per_row = "2 n d" if w.omega == "gauss" else "n (log2 d + 1)"
     return {"value": flops / el / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+            "nproc": os.cpu_count(), "cpu_model": model,
             "sample": f"FP64 oracle sketch Y[rows,:] = K_f[rows,:] Omega for {rows_done} random rows of the "
                       f"n={w.n}, d={w.d} workload ({el:.1f} s; {per_row} flops per row)"}
+
+
+def _event_ms(fn, reps: int, torch, stream) -> float:
+    """Mean duration of fn() over reps, HIP events on the launch stream."""
+    fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def srht_sketch_rates(name: str, reps: int, torch, api, W, dev) -> dict:
+    """SRHT sketch at a workload: time per launch, kernel evaluations/s and
+    transform adds/s against the plain FP32 add rate."""
+    w = W.WORKLOADS[name]
+    x = torch.from_numpy(W.points(w)).to(dev)
+    signs, cols = W.srht_draw(w)
+    om = api.Omega.srht(signs, cols, dev)
+    hyp = api.Hyper(w.kernel, w.ell, w.s)
+    stream = torch.cuda.current_stream(dev)
+    ms = _event_ms(lambda: api.sketch(x, hyp, om, w.prec), reps, torch, stream)
+    ms_fused = _event_ms(lambda: api.sketch(x, hyp, om, w.prec, want_yprime=True), reps, torch, stream)
+    adds = w.n * w.n * (math.log2(w.d) + 1.0)
+    return {"workload": f"{name}: n={w.n} D={w.D} {w.kernel} SRHT d={w.d} {w.prec}", "ms": ms,
+            "ms_fused_with_dlogell": ms_fused, "kernel_evals_per_s": w.n * w.n / (ms / 1e3),
+            "adds_per_s": adds / (ms / 1e3), "alu_peak_adds_per_s": PEAKS["fp32_add_tops"] * 1e12,
+            "alu_frac": adds / (ms / 1e3) / (PEAKS["fp32_add_tops"] * 1e12)}
+
+
+def loglik_timing(torch, api, W, dev) -> dict:
+    """The log-likelihood workload (n = 32768, d = 256): forward + log-likelihood
+    and the hyperparameter backward, FP64 (nu = 0) and FP32 with the
+    stabilising shift nu = sigma2 / 10 (at nu = 0 its float32 core is indefinite)."""
+    w = W.WORKLOADS["C4"]
+    xnp = W.points(w)
+    x = torch.from_numpy(xnp).to(dev)
+    yv = W.gp_targets(w, xnp)
+    signs, cols = W.srht_draw(w)
+    om = api.Omega.srht(signs, cols, dev)
+    hyp = api.Hyper(w.kernel, w.ell, w.s)
+    stream = torch.cuda.current_stream(dev)
+    out = {"workload": f"C4: n={w.n} D={w.D} {w.kernel} SRHT d={w.d} (targets: random-Fourier-feature GP draw)"}
+    for prec, nu in (("f64", 0.0), ("f32", 0.1 * w.sigma2)):
+        dt = torch.float64 if prec == "f64" else torch.float32
+        y = torch.from_numpy(yv).to(dev, dt).reshape(-1, 1)
+        state = {}
+
+        def fwd():
+            fw = api.forward(x, hyp, om, prec, w.sigma2, y, w.leaf_rows, nu=nu, want_yprime=True)
+            api.loglik(y, fw.sol.X, fw.sol.logdet, fw.sol.info, prec)
+            state["fw"] = fw
+
+        def bwd():
+            fw = state["fw"]
+            api.backward(x, hyp, om, prec, fw.sol, fw.Q, w.sigma2, 0, y, Yprime=fw.Yprime, R=fw.R, nu=nu)
+
+        f_ms = _event_ms(fwd, 3, torch, stream)
+        b_ms = _event_ms(bwd, 3, torch, stream)
+        out[prec] = {"nu": nu, "forward_loglik_ms": f_ms, "backward_ms": b_ms,
+                     "info": int(state["fw"].sol.info.item())}
+    return out
 
 
 def main() -> int:
@@ -121,6 +198,8 @@ def main() -> int:
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the FP32 path, SRHT, apply and log-likelihood measurements")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only copy a buffer of this many MiB device to device (reference kernel for the HBM "
                          "byte counters), then exit")
@@ -213,8 +292,8 @@ def main() -> int:
         achieved = flops["sketch"] / (sk / 1e3) / 1e12
     else:
         kernel_key = "sketch_srht_kernel"
-        # plain ALU bound: lane operations of the transform (adds) against the FP32 vector peak
-        peak, unit, bound = PEAKS["fp32_tflops"] / 2.0, "Tops/s", "alu"
+        # plain ALU bound: the transform's adds against the non-packed FP32 add rate
+        peak, unit, bound = PEAKS["fp32_add_tops"], "Tops/s", "alu"
         achieved = flops["sketch"] / (sk / 1e3) / 1e12
     traffic = read_traffic(kernel_key, src)
     roofline = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
@@ -248,6 +327,38 @@ def main() -> int:
         result["fp64_path"] = {"ms_per_step": ms64, "tflops": flops["total"] / (ms64 / 1e3) / 1e12,
                                "speedup_of_mixed": ms64 / ms, "x_rel_diff_vs_fp64": rel,
                                "logdet_rel_diff_vs_fp64": ld_rel}
+
+    if not args.no_extras and w.name == "C3":
+        # the FP32 path on the same workload: float32 kernel tiles on FP32 matrix cores
+        om32 = api.Omega.gauss(om_np["omega_t"], "f32", dev)
+        sk32 = _event_ms(lambda: api.sketch(X, hyp, om32, "f32"), 1, torch, stream)
+        out32 = step("f32", om32, Ad)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(2):
+            out32 = step("f32", om32, Ad)
+        torch.cuda.synchronize()
+        ms32 = (time.perf_counter() - t0) / 2 * 1e3
+        f32 = {"ms_per_step": ms32, "tflops": flops["total"] / (ms32 / 1e3) / 1e12, "sketch_ms": sk32,
+               "sketch_frac_of_fp32_mfma_peak": flops["sketch"] / (sk32 / 1e3) / 1e12 / PEAKS["fp32_tflops"]}
+        if "fp64_path" in result:
+            xb = out64.sol.X
+            f32["x_rel_diff_vs_fp64"] = ((out32.sol.X.double() - xb).abs().max() / xb.abs().max()).item()
+            f32["logdet_rel_diff_vs_fp64"] = abs(out32.sol.logdet.item() - out64.sol.logdet.item()) / abs(
+                out64.sol.logdet.item())
+        result["fp32_path"] = f32
+        del om32, out32
+        # Woodbury apply: lowrank_solve with the m right-hand sides minus without
+        Q, R = out.Q, out.R
+        ms_m = _event_ms(lambda: api.lowrank_solve(Q, R, om, prec, w.sigma2, Ad), 5, torch, stream)
+        ms_0 = _event_ms(lambda: api.lowrank_solve(Q, R, om, prec, w.sigma2, None), 5, torch, stream)
+        app_ms = max(ms_m - ms_0, 1e-6)
+        app_bytes = 2.0 * w.n * w.d * 4 + 3.0 * w.n * w.m * 4  # Q twice, A twice, X once
+        result["apply"] = {"ms": app_ms, "algorithmic_bytes": app_bytes, "gbs": app_bytes / (app_ms / 1e3) / 1e9,
+                           "frac_of_hbm_peak": app_bytes / (app_ms / 1e3) / 1e9 / PEAKS["hbm_gbs"]}
+        result["srht"] = [srht_sketch_rates("C2", 3, torch, api, W, dev),
+                          srht_sketch_rates("C5", 1, torch, api, W, dev)]
+        result["loglik"] = loglik_timing(torch, api, W, dev)
 
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w, x, om_np, flops["sketch"])

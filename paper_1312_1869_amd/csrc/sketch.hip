@@ -3,13 +3,15 @@
 // This file: the points prescale and the SRHT kernel (sketch_dense.hip holds the
 // dense-Omega kernel).
 //  * sketch_srht_kernel: Omega = c D H P (Def. 1, Walsh-Hadamard T). Row i of
-//    Y is c (H (D o k_i))[P]. With H_n = H_{n/4096} (x) H_4096, each 4096-long
-//    chunk j1 of D o k_i is transformed in full (12 butterfly stages: 6 over the
-//    register index, an LDS transpose, 6 more), and every selected output
-//    P_k = p1 * 4096 + p2 adds (-1)^popcount(j1 & p1) times entry p2 of the
-//    chunk transform. One wave owns one row; lane l owns outputs l, l+64, ...
-//    Work per row: n (12 + 1) butterflies/adds + d n / 4096 selections, against
-//    the 2 n d of the dense product the structure avoids (Sec. 1, Sec. 3.2).
+//    Y is c (H (D o k_i))[P]. With H_n = H_{n/2048} (x) H_2048, each 2048-long
+//    chunk j1 of D o k_i is transformed in full (11 butterfly stages: 5 over
+//    the register index, an LDS transpose, 5 more and one lane swap), and
+//    every selected output P_k = p1 * 2048 + p2 adds (-1)^popcount(j1 & p1)
+//    times entry p2 of the chunk transform. A wave owns two rows (float; they
+//    share every point load) or one row with its value and derivative sketch
+//    (the fused mode); lane l owns outputs l, l+64, ... Work per row:
+//    n (11 + 1) butterflies/adds + d n / 2048 selections, against the 2 n d of
+//    the dense product the structure avoids (Sec. 1, Sec. 3.2).
 #include <type_traits>
 
 #include "common.hpp"
@@ -50,16 +52,17 @@ template hipError_t launch_prep_points<double>(hipStream_t, const float*, int64_
 
 // ------------------------------------------------------------------ SRHT
 
-constexpr int kChunk = 4096;
-constexpr int kChunkPad = kChunk + kChunk / 64;
-__device__ __forceinline__ int padidx(int i) { return i + (i >> 6); }
+constexpr int kChunk = 2048;        // chunk of j transformed at once
+constexpr int kChunkRegs = kChunk / 64;
+constexpr int kBufWords = 2112;     // per wave: 32 x 65 (transpose) and 64 x 33 (selection) layouts
+constexpr int kLoadGroup = 8;       // point loads issued together
 
-template <typename T>
-__device__ __forceinline__ void fwht64(T (&v)[64]) {
+template <typename T, int N>
+__device__ __forceinline__ void fwht_regs(T (&v)[N]) {
 #pragma unroll
-  for (int h = 1; h < 64; h <<= 1) {
+  for (int h = 1; h < N; h <<= 1) {
 #pragma unroll
-    for (int i = 0; i < 64; ++i) {
+    for (int i = 0; i < N; ++i) {
       if ((i & h) == 0) {
         T a = v[i], b = v[i + h];
         v[i] = a + b;
@@ -98,29 +101,43 @@ template <> struct PointLoad<float, 16> : PointLoadGeneric<float, 16> {};
 template <> struct PointLoad<double, 8> : PointLoadGeneric<double, 8> {};
 template <> struct PointLoad<double, 16> : PointLoadGeneric<double, 16> {};
 
-// One chunk of values v (register r of lane l = chunk entry r*64 + l) is
-// transformed and its selected entries accumulated into acc.
+// Walsh-Hadamard transform of one 2048-long chunk and accumulation of its
+// selected entries. On entry register r of lane l holds chunk entry r*64 + l.
+//   1. stages over entry bits 6..10: butterflies across the 32 registers;
+//   2. LDS transpose (32 x 65 words): lane l then holds entries l*32 + t;
+//   3. stages over bits 0..4 across the registers, and bit 5 (lane bit 0)
+//      by a lane swap (DPP quad_perm [1,0,3,2]);
+//   4. the transformed chunk goes to LDS (64 x 33 words) and each selected
+//      output P_k = p1 * 2048 + p2 adds (-1)^popcount(chunk & p1) times entry p2.
 template <typename T, int NQ>
-__device__ __forceinline__ void srht_chunk_accumulate(T (&v)[64], T* buf, int lane, int64_t chunk,
+__device__ __forceinline__ void srht_chunk_accumulate(T (&v)[kChunkRegs], T* buf, int lane, int64_t chunk,
                                                       const int (&pk)[NQ], int d, T (&acc)[NQ]) {
-  fwht64(v);  // stages over entry bits 6..11 (register index)
+  fwht_regs(v);
 #pragma unroll
-  for (int r = 0; r < 64; ++r) buf[r * 65 + lane] = v[r];
+  for (int r = 0; r < kChunkRegs; ++r) buf[r * 65 + lane] = v[r];
   __builtin_amdgcn_wave_barrier();
+  const int rbase = (lane >> 1) * 65 + (lane & 1) * 32;
 #pragma unroll
-  for (int r = 0; r < 64; ++r) v[r] = buf[lane * 65 + r];
-  fwht64(v);  // stages over entry bits 0..5
+  for (int t = 0; t < kChunkRegs; ++t) v[t] = buf[rbase + t];
+  __builtin_amdgcn_wave_barrier();
+  fwht_regs(v);
+  const T sgn = (lane & 1) ? (T)-1 : (T)1;
 #pragma unroll
-  for (int r = 0; r < 64; ++r) buf[lane * 65 + r] = v[r];
+  for (int t = 0; t < kChunkRegs; ++t) {
+    const T partner = dpp_move<0xB1>(v[t]);
+    v[t] = __builtin_fma(sgn, v[t], partner);
+  }
+#pragma unroll
+  for (int t = 0; t < kChunkRegs; ++t) buf[lane * 33 + t] = v[t];
   __builtin_amdgcn_wave_barrier();
   const unsigned hi = (unsigned)chunk;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int k = lane + 64 * q;
     if (k < d) {
-      const int p = pk[q];
-      T val = buf[padidx(p & (kChunk - 1))];
-      const unsigned par = __popc(hi & (unsigned)(p >> 12)) & 1u;
+      const int p2 = pk[q] & (kChunk - 1);
+      const T val = buf[(p2 >> 5) * 33 + (p2 & 31)];
+      const unsigned par = __popc(hi & (unsigned)(pk[q] >> 11)) & 1u;
       acc[q] += par ? -val : val;
     }
   }
@@ -128,15 +145,19 @@ __device__ __forceinline__ void srht_chunk_accumulate(T (&v)[64], T* buf, int la
 }
 
 // MODE: 0 = Y only, 1 = Yprime only, 2 = both (fused, one kernel evaluation).
-template <typename T, int KERNEL, int PD, int ND, int NQ, int MODE>
+// R rows per wave (they share every point load); NV = R value vectors, or 2
+// (value and derivative) in the fused mode with R = 1.
+template <typename T, int KERNEL, int PD, int ND, int NQ, int MODE, int R>
 __global__ __launch_bounds__(256) void sketch_srht_kernel(const T* __restrict__ pts,
                                                           const int32_t* __restrict__ cols, int64_t n,
                                                           int d, T scale_out, T nu_c,
                                                           T* __restrict__ Y, T* __restrict__ Yp) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+  static_assert(MODE != 2 || R == 1, "the fused mode keeps two vectors of one row");
+  constexpr int NV = MODE == 2 ? 2 : R;
+  __shared__ __align__(16) T smem[4 * kBufWords];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  T* buf = reinterpret_cast<T*>(smem_raw) + wave * kChunkPad;
+  T* buf = smem + wave * kBufWords;
   using K = KernelT<T, KERNEL>;
 
   int pk[NQ];
@@ -146,66 +167,81 @@ __global__ __launch_bounds__(256) void sketch_srht_kernel(const T* __restrict__ 
     pk[q] = (k < d) ? cols[k] : 0;
   }
   const int64_t nchunks = (n + kChunk - 1) / kChunk;
-  const int64_t stride = (int64_t)gridDim.x * 4;
+  const int64_t ngroups = (n + 4 * R - 1) / (4 * R);
 
-  for (int64_t i = (int64_t)blockIdx.x * 4 + wave; i < n; i += stride) {
-    T xi[PD];
-    PointLoad<T, PD>::get(pts + i * PD, xi);
-    T acc[NQ], accd[NQ];
+  for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    const int64_t i0 = g * (4 * R) + (int64_t)wave * R;
+    T xi[R][PD];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) { acc[q] = 0; accd[q] = 0; }
+    for (int rr = 0; rr < R; ++rr) {
+      const int64_t i = i0 + rr < n ? i0 + rr : n - 1;
+      PointLoad<T, PD>::get(pts + i * PD, xi[rr]);
+    }
+    T acc[NV][NQ];
+#pragma unroll
+    for (int u = 0; u < NV; ++u)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) acc[u][q] = 0;
 
     for (int64_t c = 0; c < nchunks; ++c) {
       const int64_t base = c * kChunk;
-      const bool full = base + kChunk <= n;
-      T v[64];
-      T vd[MODE == 2 ? 64 : 1];
+      // entries past n (a partial chunk when n < 2048) read row n of the
+      // point array, a zero row whose sign slot is 0, so they contribute 0
+      const int last = (int)(n - base < kChunk ? n - base : kChunk);
+      const T* cpts = pts + base * PD;
+      T v[NV][kChunkRegs];
 #pragma unroll
-      for (int r = 0; r < 64; ++r) {
-        const int64_t j = base + r * 64 + lane;
-        T val = 0, dval = 0;
-        if (full || j < n) {
-          T pj[PD];
-          PointLoad<T, PD>::get(pts + j * PD, pj);
+      for (int r = 0; r < kChunkRegs; ++r) {
+        // at most kLoadGroup point loads in flight per wave
+        if (r % kLoadGroup == 0) __builtin_amdgcn_sched_barrier(0);
+        int jl = r * 64 + lane;
+        jl = jl < last ? jl : last;
+        T pj[PD];
+        PointLoad<T, PD>::get(cpts + jl * PD, pj);
+        const T sg = pj[PD - 1];
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
           T r2 = 0;
 #pragma unroll
           for (int t = 0; t < ND; ++t) {
-            const T df = xi[t] - pj[t];
-            r2 += df * df;
+            const T df = xi[rr][t] - pj[t];
+            r2 = __builtin_fma(df, df, r2);
           }
-          const T sg = pj[PD - 1];
           if constexpr (MODE == 0) {
-            val = sg * K::value(r2);
+            v[rr][r] = sg * K::value(r2);
           } else if constexpr (MODE == 1) {
-            val = sg * K::deriv(r2);
+            v[rr][r] = sg * K::deriv(r2);
           } else {
+            T val, dval;
             K::both(r2, val, dval);
-            val *= sg;
-            dval *= sg;
+            v[0][r] = sg * val;
+            v[1][r] = sg * dval;
           }
         }
-        v[r] = val;
-        if constexpr (MODE == 2) vd[r] = dval;
       }
-      srht_chunk_accumulate<T, NQ>(v, buf, lane, c, pk, d, acc);
-      if constexpr (MODE == 2) srht_chunk_accumulate<T, NQ>(vd, buf, lane, c, pk, d, accd);
+#pragma unroll
+      for (int u = 0; u < NV; ++u) srht_chunk_accumulate<T, NQ>(v[u], buf, lane, c, pk, d, acc[u]);
     }
 
-    const T sgi = xi[PD - 1];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int k = lane + 64 * q;
-      if (k < d) {
-        if constexpr (MODE != 1) {
-          T y = scale_out * acc[q];
-          if (nu_c != (T)0) {
+    for (int u = 0; u < NV; ++u) {
+      const int rr = MODE == 2 ? 0 : u;
+      const int64_t i = i0 + rr;
+      if (i >= n) continue;
+      T* out = (MODE == 1 || (MODE == 2 && u == 1)) ? Yp : Y;
+      const bool value = !(MODE == 1 || (MODE == 2 && u == 1));
+      const T sgi = xi[rr][PD - 1];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int k = lane + 64 * q;
+        if (k < d) {
+          T y = scale_out * acc[u][q];
+          if (value && nu_c != (T)0) {
             const unsigned par = __popcll((unsigned long long)i & (unsigned long long)pk[q]) & 1u;
             y += par ? -nu_c * sgi : nu_c * sgi;
           }
-          Y[i * d + k] = y;
+          out[i * d + k] = y;
         }
-        if constexpr (MODE == 1) Yp[i * d + k] = scale_out * acc[q];
-        if constexpr (MODE == 2) Yp[i * d + k] = scale_out * accd[q];
       }
     }
   }
@@ -214,16 +250,18 @@ __global__ __launch_bounds__(256) void sketch_srht_kernel(const T* __restrict__ 
 template <typename T, int KERNEL, int PD, int ND, int NQ, int MODE>
 static hipError_t launch_srht_impl(hipStream_t st, const T* pts, const int32_t* cols, int64_t n, int d,
                                    double scale_out, double nu_c, T* Y, T* Yp, int num_cu) {
-  const size_t lds = 4 * kChunkPad * sizeof(T);
-  auto kfn = sketch_srht_kernel<T, KERNEL, PD, ND, NQ, MODE>;
-  hipError_t e = hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  // two rows per wave share the point loads (float, separate passes); the
+  // fused mode keeps value and derivative of one row; double keeps one row
+  constexpr int R = (sizeof(T) == 4 && MODE != 2) ? 2 : 1;
+  auto kfn = sketch_srht_kernel<T, KERNEL, PD, ND, NQ, MODE, R>;
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kfn, 256, 0);
   if (e != hipSuccess) return e;
-  const int per_cu = sizeof(T) == 4 ? 2 : 1;
-  int64_t blocks = (n + 3) / 4;
+  if (per_cu < 1) per_cu = 1;
+  int64_t blocks = (n + 4 * R - 1) / (4 * R);
   const int64_t cap = (int64_t)num_cu * per_cu;
   if (blocks > cap) blocks = cap;
-  hipLaunchKernelGGL(kfn, dim3((unsigned)blocks), dim3(256), lds, st, pts, cols, n, d, (T)scale_out, (T)nu_c,
-                     Y, Yp);
+  hipLaunchKernelGGL(kfn, dim3((unsigned)blocks), dim3(256), 0, st, pts, cols, n, d, (T)scale_out, (T)nu_c, Y, Yp);
   return hipGetLastError();
 }
 
