@@ -224,7 +224,7 @@ def main() -> int:
         return 0
     w = W.WORKLOADS[args.workload]
     prec = w.prec
-    rp = "f32" if prec == "bf16" else prec
+    rp = "f32" if prec in ("bf16", "bf16x2") else prec
     rdt = torch.float64 if rp == "f64" else torch.float32
 
     # ---- inputs (host generation, then resident in HBM before timing)
@@ -348,6 +348,27 @@ def main() -> int:
                 out64.sol.logdet.item())
         result["fp32_path"] = f32
         del om32, out32
+        # the two-term bf16 sketch (K to 16 bits, two bf16 products per tile)
+        omx2 = api.Omega.gauss(om_np["omega_t"], "bf16x2", dev)
+        skx2 = _event_ms(lambda: api.sketch(X, hyp, omx2, "bf16x2"), 3, torch, stream)
+        outx2 = step("bf16x2", omx2, Ad)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            outx2 = step("bf16x2", omx2, Ad)
+        torch.cuda.synchronize()
+        msx2 = (time.perf_counter() - t0) / 3 * 1e3
+        x2 = {"ms_per_step": msx2, "tflops": flops["total"] / (msx2 / 1e3) / 1e12, "sketch_ms": skx2,
+              "sketch_bf16_products_per_s": 2.0 * flops["sketch"] / (skx2 / 1e3) / 1e12,
+              "sketch_frac_of_bf16_mfma_peak": 2.0 * flops["sketch"] / (skx2 / 1e3) / 1e12 / PEAKS["bf16_tflops"]}
+        if "fp64_path" in result:
+            xb = out64.sol.X
+            x2["x_rel_diff_vs_fp64"] = ((outx2.sol.X.double() - xb).abs().max() / xb.abs().max()).item()
+            x2["logdet_rel_diff_vs_fp64"] = abs(outx2.sol.logdet.item() - out64.sol.logdet.item()) / abs(
+                out64.sol.logdet.item())
+            x2["speedup_vs_fp64"] = result["fp64_path"]["ms_per_step"] / msx2
+        result["bf16x2_path"] = x2
+        del omx2, outx2
         # Woodbury apply: lowrank_solve with the m right-hand sides minus without
         Q, R = out.Q, out.R
         ms_m = _event_ms(lambda: api.lowrank_solve(Q, R, om, prec, w.sigma2, Ad), 5, torch, stream)

@@ -34,7 +34,10 @@
  *     tiles, sketch and leaf QR; float64 tree, d x d core and solves),
  *     LR_PREC_BF16 (as F32, but the dense-Omega sketch rounds K tiles to
  *     bfloat16 and runs on bf16 matrix cores with float32 accumulation;
- *     n <= 2^25, else LR_ERR_UNSUPPORTED).
+ *     n <= 2^25, else LR_ERR_UNSUPPORTED), LR_PREC_BF16X2 (as BF16, but each
+ *     kernel entry k is split into k_hi = bf16(k) and k_lo = bf16(k - k_hi),
+ *     and both products with the bf16 Omega run on the matrix cores: K is
+ *     carried to about 16 bits instead of 8; dense Omega with D <= 3 only).
  *     "real" below means double for F64 and float otherwise.
  *   - Points X are float32 n x D (1 <= D <= 15) in every precision.
  *   - Sizes: n >= 1, 1 <= d <= 1024, d <= n, 0 <= m <= 64.
@@ -62,7 +65,7 @@ typedef enum {
 
 typedef enum { LR_KERNEL_SE = 0, LR_KERNEL_MATERN32 = 1 } lr_kernel;
 typedef enum { LR_OMEGA_SRHT = 0, LR_OMEGA_GAUSS = 1 } lr_omega_kind;
-typedef enum { LR_PREC_F64 = 0, LR_PREC_F32 = 1, LR_PREC_BF16 = 2 } lr_prec;
+typedef enum { LR_PREC_F64 = 0, LR_PREC_F32 = 1, LR_PREC_BF16 = 2, LR_PREC_BF16X2 = 3 } lr_prec;
 
 /* Stationary kernel (Sec. 5.1 forms):
  *   LR_KERNEL_SE       k(r) = s^2 exp(-r^2 / (2 ell^2))
@@ -84,7 +87,7 @@ typedef struct {
  *   LR_OMEGA_GAUSS (dense, e.g. i.i.d. N(0, 1/d), Sec. 3.1):
  *       dense_t: device, Omega TRANSPOSED, d rows of length >= n with leading
  *       dimension ld (elements, ld >= n, ld % 8 == 0, 16-byte aligned base),
- *       element type double (F64), float (F32) or bfloat16 bits (BF16). */
+ *       element type double (F64), float (F32) or bfloat16 bits (BF16, BF16X2). */
 typedef struct {
   int32_t kind;        /* lr_omega_kind */
   int32_t d;
@@ -110,7 +113,7 @@ lr_status lr_check_srht_cols(const int32_t *cols_host, int32_t d, int64_t n);
  *   Y       device real n x d output (may be NULL when only Yprime is wanted).
  *   Yprime  device real n x d output of (dK_f / dlog ell) Omega, or NULL. With
  *           SRHT and F32 both outputs come from one fused pass.
- * Unsupported: BF16 with SRHT.
+ * Unsupported: BF16 and BF16X2 with SRHT; BF16X2 with D > 3.
  * Workspace: the prescaled points ((n + 128) rows) and, for BF16 with D <= 3, a
  * copy of the Gaussian Omega in matrix-core operand order (about 2 n d bytes). */
 size_t lr_sketch_workspace_bytes(int64_t n, int32_t D, int32_t d, int32_t prec);

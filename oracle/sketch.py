@@ -11,9 +11,12 @@ Omega is described by a small dict:
   {"kind": "srht", "signs": int8[n], "cols": int32[d]}
   {"kind": "gauss", "omega_t": float[d, n]}   (Omega stored transposed)
 
-Precision model (for the bf16 matrix-core path): ``k_round="bf16"`` rounds each
-K_f entry to bfloat16 (round to nearest even) before the product; Omega is
-already bf16-valued in that workload. Default: no rounding.
+Precision model (for the bf16 matrix-core paths): ``k_round="bf16"`` rounds each
+K_f entry to bfloat16 (round to nearest even) before the product;
+``k_round="bf16x2"`` replaces each entry k by k_hi + k_lo with k_hi = bf16(k)
+and k_lo = bf16(k - k_hi) (a two-term split that keeps about 16 bits, the
+product of both terms with Omega summed). Omega is already bf16-valued in
+that workload. Default: no rounding.
 
 Pins (tests/test_oracle_sketch.py): explicit dense K_f @ Omega on small n for
 both Omega kinds; the row-sampled form against the full product; linearity in
@@ -53,6 +56,13 @@ def round_to_bf16(a: np.ndarray) -> np.ndarray:
     return np.ldexp(np.rint(mant * 256.0), expo - 8)
 
 
+def round_to_bf16x2(a: np.ndarray) -> np.ndarray:
+    """k_hi + k_lo with k_hi = bf16(k), k_lo = bf16(k - k_hi), summed in float64."""
+    a = np.asarray(a, dtype=np.float64)
+    hi = round_to_bf16(a)
+    return hi + round_to_bf16(a - hi)
+
+
 def _right_apply(kblock: np.ndarray, omega: dict) -> np.ndarray:
     if omega["kind"] == "srht":
         return srht.right_apply(kblock, omega["signs"], omega["cols"])
@@ -79,6 +89,8 @@ def sketch_rows(x: np.ndarray, rows: np.ndarray, kind: str, ell: float, s: float
             kb = kernels.kernel_matrix(kind, x64[rb], x64, ell, s)
         if k_round == "bf16":
             kb = round_to_bf16(kb)
+        elif k_round == "bf16x2":
+            kb = round_to_bf16x2(kb)
         out[b0:b0 + block] = _right_apply(kb, omega)
     if nu != 0.0 and not deriv:
         out += nu * omega_rows(omega, rows)

@@ -15,9 +15,9 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblrinv.so
 NOALLOC_SCRATCH_BYTES = 32 << 20
 LR_KERNEL_SE, LR_KERNEL_MATERN32 = 0, 1
 LR_OMEGA_SRHT, LR_OMEGA_GAUSS = 0, 1
-LR_PREC_F64, LR_PREC_F32, LR_PREC_BF16 = 0, 1, 2
+LR_PREC_F64, LR_PREC_F32, LR_PREC_BF16, LR_PREC_BF16X2 = 0, 1, 2, 3
 
-PRECS = {"f64": LR_PREC_F64, "f32": LR_PREC_F32, "bf16": LR_PREC_BF16}
+PRECS = {"f64": LR_PREC_F64, "f32": LR_PREC_F32, "bf16": LR_PREC_BF16, "bf16x2": LR_PREC_BF16X2}
 KERNELS = {"se": LR_KERNEL_SE, "matern32": LR_KERNEL_MATERN32}
 
 c_i32, c_i64, c_dbl, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t

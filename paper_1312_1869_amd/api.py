@@ -81,7 +81,7 @@ class Omega:
         """Omega given transposed (d x n); stored d x ld with ld = n rounded up to 64."""
         d, n = omega_t.shape
         ld = (n + 63) // 64 * 64
-        dt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[prec]
+        dt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "bf16x2": torch.bfloat16}[prec]
         host = torch.zeros((d, ld), dtype=torch.float32)
         host[:, :n] = torch.from_numpy(np.ascontiguousarray(omega_t, dtype=np.float32))
         if prec == "f64":

@@ -57,7 +57,10 @@ size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 bool is_fin(double x) { return isfinite(x) != 0; }
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 size_t real_size(int32_t prec) { return prec == LR_PREC_F64 ? 8 : 4; }
-bool valid_prec(int32_t prec) { return prec == LR_PREC_F64 || prec == LR_PREC_F32 || prec == LR_PREC_BF16; }
+bool valid_prec(int32_t prec) {
+  return prec == LR_PREC_F64 || prec == LR_PREC_F32 || prec == LR_PREC_BF16 || prec == LR_PREC_BF16X2;
+}
+bool bf16_sketch(int32_t prec) { return prec == LR_PREC_BF16 || prec == LR_PREC_BF16X2; }
 
 lr_status check_ws(size_t need, const void* ws, size_t ws_bytes) {
   if (need == 0) return LR_OK;
@@ -79,14 +82,14 @@ lr_status check_omega(const lr_omega* o, int64_t n, int32_t d, int32_t prec) {
   if (o->kind == LR_OMEGA_SRHT) {
     if ((n & (n - 1)) != 0) return LR_ERR_NOT_POW2;
     if (o->signs == nullptr || o->cols == nullptr) return LR_ERR_ARG;
-    if (prec == LR_PREC_BF16) return LR_ERR_UNSUPPORTED;
+    if (bf16_sketch(prec)) return LR_ERR_UNSUPPORTED;
     return LR_OK;
   }
   if (o->kind == LR_OMEGA_GAUSS) {
     if (o->dense_t == nullptr || !aligned(o->dense_t, 16)) return LR_ERR_ARG;
     if (o->ld < n || o->ld % 8 != 0) return LR_ERR_SHAPE;
     // the bf16 sketch addresses Omega through 31-bit buffer extents
-    if (prec == LR_PREC_BF16 && n > ((int64_t)1 << 25)) return LR_ERR_UNSUPPORTED;
+    if (bf16_sketch(prec) && n > ((int64_t)1 << 25)) return LR_ERR_UNSUPPORTED;
     return LR_OK;
   }
   return LR_ERR_ARG;
@@ -141,7 +144,7 @@ size_t sketch_pts_bytes(int64_t n, int32_t D, int32_t prec) {
 // copy of a Gaussian Omega
 size_t sketch_ws(int64_t n, int32_t D, int32_t d, int32_t prec) {
   size_t b = sketch_pts_bytes(n, D, prec);
-  if (prec == LR_PREC_BF16 && D <= 3) b += al(omega_frag_bytes(n, d));
+  if (bf16_sketch(prec) && D <= 3) b += al(omega_frag_bytes(n, d));
   return b;
 }
 
@@ -173,7 +176,7 @@ lr_status sketch_impl(hipStream_t st, int64_t n, int32_t D, const float* X, cons
     LR_HIP(launch_prep_points<float>(st, X, n, D, PD, scale, nullptr, static_cast<float*>(ws)));
   }
   void* frag = nullptr;
-  if (prec == LR_PREC_BF16 && D <= 3) {
+  if (bf16_sketch(prec) && D <= 3) {
     frag = static_cast<char*>(ws) + sketch_pts_bytes(n, D, prec);
     LR_HIP(launch_omega_frag(st, omega->dense_t, omega->ld, n, d, frag));
   }
@@ -362,6 +365,7 @@ lr_status lr_sketch(void* stream, int64_t n, int32_t D, const float* X, const lr
   if (X == nullptr || (Y == nullptr && Yprime == nullptr)) return LR_ERR_ARG;
   if ((s = check_hyper(hyp)) != LR_OK) return s;
   if ((s = check_omega(omega, n, omega->d, prec)) != LR_OK) return s;
+  if (prec == LR_PREC_BF16X2 && D > 3) return LR_ERR_UNSUPPORTED;
   if (!is_fin(nu) || nu < 0.0) return LR_ERR_ARG;
   if ((s = check_ws(sketch_ws(n, D, omega->d, prec), ws, ws_bytes)) != LR_OK) return s;
   return sketch_impl(static_cast<hipStream_t>(stream), n, D, X, hyp, omega, nu, prec, Y, Yprime, ws);
@@ -379,7 +383,8 @@ lr_status lr_sketch_noalloc(void* stream, int64_t n, int32_t D, const float* X, 
   if ((s = check_omega(omega, n, omega->d, prec)) != LR_OK) return s;
   if (!is_fin(nu) || nu < 0.0) return LR_ERR_ARG;
   // the bf16 matrix-core sketch with D <= 3 reads a 2 n d byte operand copy of Omega
-  if (prec == LR_PREC_BF16 && D <= 3 && omega->kind == LR_OMEGA_GAUSS) return LR_ERR_UNSUPPORTED;
+  if (bf16_sketch(prec) && D <= 3 && omega->kind == LR_OMEGA_GAUSS) return LR_ERR_UNSUPPORTED;
+  if (prec == LR_PREC_BF16X2 && D > 3) return LR_ERR_UNSUPPORTED;
   if (sketch_ws(n, D, omega->d, prec) > kNoAllocBytes) return LR_ERR_SCRATCH_LIMIT;
   void* ws = scratch_current();
   if (ws == nullptr) return LR_ERR_HIP;
@@ -474,6 +479,7 @@ lr_status lr_backward(void* stream, int64_t n, int32_t D, const float* X, const 
   if (s != LR_OK) return s;
   if ((s = check_hyper(hyp)) != LR_OK) return s;
   if ((s = check_omega(omega, n, d, prec)) != LR_OK) return s;
+  if (prec == LR_PREC_BF16X2 && D > 3) return LR_ERR_UNSUPPORTED;
   if (mode != 0 && mode != 1) return LR_ERR_ARG;
   if (mode == 0 && m != 1) return LR_ERR_SHAPE;
   if (mode == 1 && (m < 1 || m > 64)) return LR_ERR_SHAPE;

@@ -407,7 +407,7 @@ __device__ __forceinline__ float row_bcast(float v) {
                                                                false));
 }
 
-template <int NW, int KERNEL, int PD, int ND, int WC, bool DERIV>
+template <int NW, int KERNEL, int PD, int ND, int WC, bool DERIV, bool X2>
 __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __restrict__ pts,
                                                                  const uint4* __restrict__ frag, int64_t nst,
                                                                  const uint16_t* __restrict__ omt, int64_t ld,
@@ -417,14 +417,20 @@ __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __
   using Frag = OmegaFrag<LR_PREC_BF16>;
   constexpr int BN = NW * 16 * WC;
   constexpr int GPT = 64 / NW;  // kernel entries per thread per step (8 or 16)
+  // X2: every entry k is split into k_hi = bf16(k) and k_lo = bf16(k - k_hi),
+  // two tiles and two products per fragment (NFR fragment reads per step)
+  constexpr int NFR = X2 ? 16 : 8;
+  constexpr int NMF = NFR * WC;
+  constexpr int kTileHalf = 4 * kDenseRows * 8;
 #ifdef LR_B16_VALU_PER_MFMA
   constexpr int kValuPerMfma = LR_B16_VALU_PER_MFMA;
 #else
-  constexpr int kValuPerMfma = (9 * GPT / (8 * WC)) > 2 ? (9 * GPT / (8 * WC)) : 2;
+  constexpr int kValuPerMfma = X2 ? ((11 * GPT / (16 * WC)) > 1 ? (11 * GPT / (16 * WC)) : 1)
+                                  : ((9 * GPT / (8 * WC)) > 2 ? (9 * GPT / (8 * WC)) : 2);
 #endif
   static_assert(NW == 4 || NW == 8, "4 or 8 waves");
 
-  __shared__ __align__(16) __bf16 tile[2][4 * kDenseRows * 8];  // [buf][k-group][row][8]
+  __shared__ __align__(16) __bf16 tile[2][(X2 ? 2 : 1) * kTileHalf];  // [buf][hi/lo][k-group][row][8]
 
   const int tid = threadIdx.x;
   const int w = wave_uniform(tid >> 6);
@@ -481,6 +487,7 @@ __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __
       }
     };
     __bf16 gen[GPT];
+    __bf16 genlo[X2 ? GPT : 1];
     auto generate = [&](const Pts& p) {
       static_for<0, GPT>([&](auto ee) {
         constexpr int e = decltype(ee)::value;
@@ -490,7 +497,9 @@ __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __
           const float df = row_bcast<e>(p[t]) - xi[t];
           r2 = __builtin_fmaf(df, df, r2);
         }
-        gen[e] = (__bf16)(DERIV ? K::deriv(r2) : K::value(r2));
+        const float kv = DERIV ? K::deriv(r2) : K::value(r2);
+        gen[e] = (__bf16)kv;
+        if constexpr (X2) genlo[e] = (__bf16)(kv - (float)gen[e]);
       });
     };
     auto store_gen = [&](int buf) {
@@ -499,6 +508,10 @@ __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __
         __bf16* dst = &tile[buf][((GPT / 8 * gg + u) * kDenseRows + grow) * 8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) dst[e] = gen[8 * u + e];
+        if constexpr (X2) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) dst[kTileHalf + e] = genlo[8 * u + e];
+        }
       }
     };
     // this wave's fragments: one buffer view per 16-column group (nst steps
@@ -528,18 +541,18 @@ __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __
       const int cur = (int)(s & 1);
       load_b(s + kB16Ahead, bl);
       load_pts(s + 3, pl);
-      Frag a[8];
+      Frag a[NFR];
 #pragma unroll
-      for (int f = 0; f < 8; ++f) {
-        const __bf16* src = &tile[cur][(fg * kDenseRows + 16 * f + fl) * 8];
+      for (int f = 0; f < NFR; ++f) {
+        const __bf16* src = &tile[cur][(f / 8) * kTileHalf + (fg * kDenseRows + 16 * (f % 8) + fl) * 8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) a[f].v[e] = src[e];
       }
       generate(pg);
 #pragma unroll
-      for (int f = 0; f < 8; ++f)
+      for (int f = 0; f < NFR; ++f)
 #pragma unroll
-        for (int c = 0; c < WC; ++c) mfma_step<LR_PREC_BF16>(acc[f][c], a[f], b[c]);
+        for (int c = 0; c < WC; ++c) mfma_step<LR_PREC_BF16>(acc[f % 8][c], a[f], b[c]);
       store_gen(cur ^ 1);
       // issue order: the tile reads and operand loads, then every
       // matrix-core operation followed by a few vector instructions of the
@@ -547,13 +560,13 @@ __global__ __launch_bounds__(NW * 64, 1) void sketch_bf16_kernel(const float* __
       if constexpr (kB16Interleave) {
         __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
         __builtin_amdgcn_sched_group_barrier(0x020, WC + 1, 0);
-        static_for<0, 8 * WC>([&](auto ii) {
+        static_for<0, NMF>([&](auto ii) {
           constexpr int i = decltype(ii)::value;
-          if constexpr (i % WC == 0 && i / WC < 6) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+          if constexpr (i % WC == 0 && i / WC < NFR - 2) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
           __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
           __builtin_amdgcn_sched_group_barrier(0x002, kValuPerMfma, 0);
         });
-        __builtin_amdgcn_sched_group_barrier(0x200, GPT / 8, 0);
+        __builtin_amdgcn_sched_group_barrier(0x200, (X2 ? 2 : 1) * GPT / 8, 0);
       }
       __syncthreads();
       // keep each step's instructions inside the step, so loads issued at its
@@ -635,7 +648,7 @@ size_t omega_frag_bytes(int64_t n, int d) {
   return ((size_t)(omega_frag_cols(d) / 16) * nst + kB16Ahead) * 64 * 16;
 }
 
-template <int KERNEL, int PD, int ND, int WC, bool DERIV>
+template <int KERNEL, int PD, int ND, int WC, bool DERIV, bool X2>
 static hipError_t launch_bf16_impl(hipStream_t st, const void* pts, const uint4* frag, const void* omt, int64_t ld,
                                    int64_t n, int d, double scale_out, double nu, void* Y, int num_cu) {
   constexpr int NW = kB16Waves;
@@ -647,23 +660,23 @@ static hipError_t launch_bf16_impl(hipStream_t st, const void* pts, const uint4*
   if (n > kBf16MaxRows) return hipErrorInvalidValue;
   int64_t blocks = (int64_t)nrb * ncb;
   if (blocks > num_cu) blocks = num_cu;
-  hipLaunchKernelGGL((sketch_bf16_kernel<NW, KERNEL, PD, ND, WC, DERIV>), dim3((unsigned)blocks), dim3(NW * 64), 0,
+  hipLaunchKernelGGL((sketch_bf16_kernel<NW, KERNEL, PD, ND, WC, DERIV, X2>), dim3((unsigned)blocks), dim3(NW * 64), 0,
                      st, (const float*)pts, frag, nst, (const uint16_t*)omt, ld, n, d, (float)scale_out, (float)nu,
                      (float*)Y, nrb, ncb);
   return hipGetLastError();
 }
 
-template <int KERNEL, int PD, int ND, bool DERIV>
+template <int KERNEL, int PD, int ND, bool DERIV, bool X2>
 static hipError_t launch_bf16_wc(hipStream_t st, const void* pts, const uint4* frag, const void* omt, int64_t ld,
                                  int64_t n, int d, double so, double nu, void* Y, int num_cu) {
   constexpr int cols_per_wc = kB16Waves * 16;
   if (d <= cols_per_wc)
-    return launch_bf16_impl<KERNEL, PD, ND, 1, DERIV>(st, pts, frag, omt, ld, n, d, so, nu, Y, num_cu);
+    return launch_bf16_impl<KERNEL, PD, ND, 1, DERIV, X2>(st, pts, frag, omt, ld, n, d, so, nu, Y, num_cu);
   if (d <= 2 * cols_per_wc)
-    return launch_bf16_impl<KERNEL, PD, ND, 2, DERIV>(st, pts, frag, omt, ld, n, d, so, nu, Y, num_cu);
+    return launch_bf16_impl<KERNEL, PD, ND, 2, DERIV, X2>(st, pts, frag, omt, ld, n, d, so, nu, Y, num_cu);
   // wider column blocks do not fit the register file with the operands;
   // larger d takes several column blocks
-  return launch_bf16_impl<KERNEL, PD, ND, 4, DERIV>(st, pts, frag, omt, ld, n, d, so, nu, Y, num_cu);
+  return launch_bf16_impl<KERNEL, PD, ND, 4, DERIV, X2>(st, pts, frag, omt, ld, n, d, so, nu, Y, num_cu);
 }
 
 hipError_t launch_omega_frag(hipStream_t st, const void* omt, int64_t ld, int64_t n, int d, void* frag) {
@@ -707,15 +720,24 @@ static hipError_t launch_dense_wn(hipStream_t st, const void* pts, const void* o
 template <int PREC, int KERNEL, bool DERIV>
 static hipError_t launch_dense_dim(hipStream_t st, int D, const void* pts, const void* omt, int64_t ld, int64_t n,
                                    int d, double so, double nu, void* Y, const void* frag, int num_cu) {
-  if constexpr (PREC == LR_PREC_BF16) {
+  if constexpr (PREC == LR_PREC_BF16X2) {
+    // the split product runs on the matrix-core kernel only (D <= 3)
+    if (D > 3 || frag == nullptr) return hipErrorInvalidValue;
+    const uint4* f = static_cast<const uint4*>(frag);
+    switch (D) {
+      case 1: return launch_bf16_wc<KERNEL, 4, 1, DERIV, true>(st, pts, f, omt, ld, n, d, so, nu, Y, num_cu);
+      case 2: return launch_bf16_wc<KERNEL, 4, 2, DERIV, true>(st, pts, f, omt, ld, n, d, so, nu, Y, num_cu);
+      default: return launch_bf16_wc<KERNEL, 4, 3, DERIV, true>(st, pts, f, omt, ld, n, d, so, nu, Y, num_cu);
+    }
+  } else if constexpr (PREC == LR_PREC_BF16) {
     // D <= 3 (point stride 4): the matrix-core kernel on the fragment copy
     if (D <= 3) {
       if (frag == nullptr) return hipErrorInvalidValue;
       const uint4* f = static_cast<const uint4*>(frag);
       switch (D) {
-        case 1: return launch_bf16_wc<KERNEL, 4, 1, DERIV>(st, pts, f, omt, ld, n, d, so, nu, Y, num_cu);
-        case 2: return launch_bf16_wc<KERNEL, 4, 2, DERIV>(st, pts, f, omt, ld, n, d, so, nu, Y, num_cu);
-        default: return launch_bf16_wc<KERNEL, 4, 3, DERIV>(st, pts, f, omt, ld, n, d, so, nu, Y, num_cu);
+        case 1: return launch_bf16_wc<KERNEL, 4, 1, DERIV, false>(st, pts, f, omt, ld, n, d, so, nu, Y, num_cu);
+        case 2: return launch_bf16_wc<KERNEL, 4, 2, DERIV, false>(st, pts, f, omt, ld, n, d, so, nu, Y, num_cu);
+        default: return launch_bf16_wc<KERNEL, 4, 3, DERIV, false>(st, pts, f, omt, ld, n, d, so, nu, Y, num_cu);
       }
     }
     if (D <= 7) return launch_dense_wn<PREC, KERNEL, 8, 7, DERIV>(st, pts, omt, ld, n, d, so, nu, Y, num_cu);
@@ -749,6 +771,11 @@ hipError_t launch_sketch_dense(hipStream_t st, int prec, int kernel, int D, cons
   if (prec == LR_PREC_BF16) {
     return deriv ? launch_dense_prec<LR_PREC_BF16, true>(st, kernel, D, pts, omt, ld, n, d, so, nu, Y, frag, num_cu)
                  : launch_dense_prec<LR_PREC_BF16, false>(st, kernel, D, pts, omt, ld, n, d, so, nu, Y, frag, num_cu);
+  }
+  if (prec == LR_PREC_BF16X2) {
+    return deriv ? launch_dense_prec<LR_PREC_BF16X2, true>(st, kernel, D, pts, omt, ld, n, d, so, nu, Y, frag, num_cu)
+                 : launch_dense_prec<LR_PREC_BF16X2, false>(st, kernel, D, pts, omt, ld, n, d, so, nu, Y, frag,
+                                                            num_cu);
   }
   if (prec == LR_PREC_F32) {
     return deriv ? launch_dense_prec<LR_PREC_F32, true>(st, kernel, D, pts, omt, ld, n, d, so, nu, Y, frag, num_cu)

@@ -41,7 +41,7 @@ def omega_pair(w: W.Workload, prec: str, dev, n: int | None = None, d: int | Non
     if w.omega == "srht":
         signs, cols = W.srht_draw(w, n, d)
         return {"kind": "srht", "signs": signs, "cols": cols}, a.Omega.srht(signs, cols, dev)
-    om_t = W.gauss_omega(w, n, d, round_bf16=(prec == "bf16"))
+    om_t = W.gauss_omega(w, n, d, round_bf16=(prec in ("bf16", "bf16x2")))
     return {"kind": "gauss", "omega_t": om_t}, a.Omega.gauss(om_t, prec, dev)
 
 

@@ -150,6 +150,33 @@ def test_dense_ragged(prec, kind):
         assert err <= 4 * math.sqrt(w.n) * u + 16 * u
 
 
+@pytest.mark.parametrize("kind", ["matern32", "se"])
+def test_dense_bf16x2(kind):
+    """Two-term bf16 split of every kernel entry (k_hi + k_lo, 16 bits). The
+    GPU splits its float32 value k32, the oracle its float64 value k; each
+    split is within 2^-16 of what it splits, so the entries differ by at most
+    2^-15 |k| plus the float32 evaluation error (16 u32 |k|), and the sums add
+    the float32 accumulation error (4 sqrt(n) u32) of the scale."""
+    dev = device()
+    w = W.small(W.WORKLOADS["C3"], 3000, d=100).replace(kernel=kind, ell=0.2)
+    x, om, y, yp = _run(w, "bf16x2", dev, want_yprime=True, nu=0.1)
+    om_t = om["omega_t"]
+    rows = np.arange(w.n)
+    sc = _scale_dense(x, rows, w, om_t) + 0.1 * np.abs(om_t.T)
+    ref = osk.sketch(x, w.kernel, w.ell, w.s, om, nu=0.1, k_round="bf16x2")
+    refd = osk.sketch(x, w.kernel, w.ell, w.s, om, deriv=True, k_round="bf16x2")
+    kd = np.abs(kernels.kernel_matrix_dlogell(w.kernel, x, x, w.ell, w.s))
+    scd = kd @ np.abs(om_t.astype(np.float64)).T
+    e1 = (np.abs(y - ref) / sc).max()
+    e2 = (np.abs(yp - refd) / scd).max()
+    exact = osk.sketch(x, w.kernel, w.ell, w.s, om, nu=0.1)
+    e3 = (np.abs(y - exact) / sc).max()
+    bar = 2.0 ** -15 + 16 * U32 + 4 * math.sqrt(w.n) * U32
+    note(f"  bf16x2 vs bf16x2 oracle: Y {e1:.3e} Y' {e2:.3e} (bar {bar:.2e}); vs exact {e3:.3e}")
+    assert e1 <= bar and e2 <= bar
+    assert e3 <= 2.0 ** -16 + bar
+
+
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 def test_dense_derivative_and_nu(prec):
     dev = device()

@@ -31,7 +31,7 @@ def _forward(w, prec, dev, nu=0.0, m=None):
     x = W.points(w)
     A = W.rhs(w, m=m)
     om_np, om = omega_pair(w, prec, dev)
-    rp = "f32" if prec == "bf16" else prec
+    rp = "f32" if prec in ("bf16", "bf16x2") else prec
     dt = torch.float64 if rp == "f64" else torch.float32
     note(f"forward {w.name} n={w.n} d={w.d} m={A.shape[1]} prec={prec} nu={nu}")
     Y, _ = a.sketch(to_dev(x, torch.float32, dev), hyper(w), om, prec, nu=nu)
@@ -138,6 +138,25 @@ def test_bf16_path_error_vs_fp64_oracle():
     assert ex <= 5e-2 and el <= 2e-4
     # against the oracle that rounds K to bf16 as the kernel does
     assert exb <= 1e-5 + 4.0 * mx and elb <= 1e-8 + 4.0 * ml
+
+
+def test_bf16x2_path_error_vs_fp64_oracle():
+    """The two-term bf16 sketch: K carried to 16 bits (the oracle's bf16x2
+    precision model), float32 leaf QR, float64 tree and core."""
+    dev = device()
+    w = W.small(W.WORKLOADS["C3"], 4096, d=128, leaf_rows=1024, m=4)
+    x, A, om_np, _, Y, Q, R, sol = _forward(w, "bf16x2", dev)
+    ref = og.forward(x, w.kernel, w.ell, w.s, w.sigma2, om_np, A, w.leaf_rows)
+    refb = og.forward(x, w.kernel, w.ell, w.s, w.sigma2, om_np, A, w.leaf_rows, k_round="bf16x2")
+    mod = _model_forward(x, w, om_np, A, Y.double().cpu().numpy())
+    ex = rel_max(sol.X.cpu().numpy(), ref["X"])
+    exb = rel_max(sol.X.cpu().numpy(), refb["X"])
+    el = abs(sol.logdet.item() - ref["logdet"]) / abs(ref["logdet"])
+    mx = rel_max(mod["X"], ref["X"])
+    ml = abs(mod["logdet"] - ref["logdet"]) / abs(ref["logdet"])
+    note(f"  BF16X2 path: X rel vs fp64 {ex:.2e} (vs bf16x2-K oracle {exb:.2e}; float32 model {mx:.2e}), "
+         f"logdet rel {el:.2e} (model {ml:.2e})")
+    assert ex <= 1e-5 + 4.0 * mx and el <= 1e-8 + 4.0 * ml
 
 
 def test_not_pd_reports_info_and_leaves_x():

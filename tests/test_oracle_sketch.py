@@ -7,7 +7,7 @@ from scipy.linalg import hadamard
 from scipy.spatial.distance import cdist
 
 import workloads as W
-from oracle import sketch
+from oracle import kernels, sketch
 
 
 def _kf(x, kind, ell, s):
@@ -64,3 +64,28 @@ def test_bf16_rounding_grid():
     assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1.0 + 2 ** -7
     bits = W.bf16_bits(v.astype(np.float32))
     np.testing.assert_array_equal(W.bf16_to_f32(bits).astype(np.float64), r)
+
+
+def test_bf16x2_split_error_bound_and_sketch():
+    """bfloat16 keeps 8 significant bits (unit roundoff u = 2^-8): k_hi = bf16(k)
+    is within u |k|, and k_lo = bf16(k - k_hi) within u of that remainder, so
+    |k_hi + k_lo - k| <= u^2 |k| = 2^-16 |k|; the error reaches the 2^-17
+    neighbourhood (the split is not exact), and the bf16x2 sketch is the plain
+    product of the split entries with Omega."""
+    rng = np.random.default_rng(8)
+    v = rng.standard_normal(200000) * np.exp(rng.uniform(-20, 5, 200000))
+    r2 = sketch.round_to_bf16x2(v)
+    rel = np.abs(r2 - v) / np.abs(v)
+    assert rel.max() <= 2.0 ** -16
+    assert rel.max() >= 2.0 ** -18
+    # one bf16 term alone is far coarser
+    assert (np.abs(sketch.round_to_bf16(v) - v) / np.abs(v)).max() >= 2.0 ** -10
+    w = W.small(W.WORKLOADS["C3"], 300, d=12)
+    x = W.points(w)
+    om = {"kind": "gauss", "omega_t": W.gauss_omega(w, round_bf16=True).astype(np.float64)}
+    k = kernels.kernel_matrix(w.kernel, x, x, w.ell, w.s)
+    hi = sketch.round_to_bf16(k)
+    lo = sketch.round_to_bf16(k - hi)
+    ref = (hi + lo) @ om["omega_t"].T
+    np.testing.assert_allclose(sketch.sketch(x, w.kernel, w.ell, w.s, om, k_round="bf16x2"), ref, rtol=1e-13,
+                               atol=1e-13 * np.abs(ref).max())
