@@ -249,6 +249,10 @@ def _golden_c4():
     return {k: float(v) for k, v in read_golden("c4_oracle_reference.txt")}
 
 
+def _golden_exact():
+    return {k: float(v) for k, v in read_golden("exact_dense_reference.txt")}
+
+
 def test_c4_full_fp32_without_shift_breaks_down_like_the_model():
     """The full log-likelihood workload at FP32 with nu = 0: the trailing
     singular values of the sketch (~1e-15 of the largest for this kernel and
@@ -309,6 +313,11 @@ def test_c4_full_fp32_shifted_loglik_and_gradient():
     note(f"  loglik {ll:.10e} oracle {gold['loglik_nu']:.10e} rel {e_ll:.2e} (samples up to {m_ll:.2e})")
     sbar = _loglik_stage_bar(r, yv, w.sigma2, g_st, nu)
     note(f"  stage-wise bar/|g| {sbar / np.abs(g_st)}")
+    ex = _golden_exact()
+    g_ex = np.array([ex["c4_" + k + "_exact"] for k in keys])
+    note(f"  against the exact dense log-likelihood (the shift is a change of method): ll error "
+         f"{ll - ex['c4_loglik_exact']:.3e} (FP64 oracle at the same shift "
+         f"{gold['loglik_nu'] - ex['c4_loglik_exact']:.3e}); grad error {r['g'] - g_ex} (oracle {g_ref - g_ex})")
     assert np.all(np.abs(r["g"] - g_st) <= sbar)
     assert np.all(np.abs(r["g"] - g_ref) <= bar)
     assert e_ll <= 1e-6 + 3.0 * m_ll
@@ -371,7 +380,16 @@ def test_c4_full_fp64_gradient():
          f"(bar {sbar / np.abs(g_st)})")
     note(f"  fd {fd} oracle {g_ref} rel vs oracle {_rel(g, g_ref)} QR backward error {beta:.2e} "
          f"bar/|g| {bar / np.abs(g_ref)}")
+    ex = _golden_exact()
+    g_ex = np.array([ex["c4_" + k + "_exact"] for k in keys])
+    note(f"  against the exact dense log-likelihood: ll error {ll0 - ex['c4_loglik_exact']:.3e} "
+         f"(oracle {gold['loglik'] - ex['c4_loglik_exact']:.3e}); grad error {g - g_ex} (oracle {g_ref - g_ex})")
     assert np.all(np.abs(g - g_st) <= sbar)
     assert np.all(np.abs(g - fd) <= 1e-7 * np.abs(g) + 2e-9 * abs(ll0) / h)
     assert abs(ll0 - gold["loglik"]) <= 1e-10 * abs(gold["loglik"])
     assert np.all(np.abs(g - g_ref) <= bar)
+    # the method itself (rank 256, no shift) is within 1e-11 of the exact
+    # log-likelihood and 3e-6 of its gradient here; the GPU adds at most its
+    # parity bars to that
+    assert abs(ll0 - ex["c4_loglik_exact"]) <= 1e-11 * abs(ex["c4_loglik_exact"]) + 1e-10 * abs(gold["loglik"])
+    assert np.all(np.abs(g - g_ex) <= 3e-6 * np.abs(g_ex) + bar)

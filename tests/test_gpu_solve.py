@@ -53,6 +53,30 @@ def test_c1_fp64_end_to_end():
     assert ex <= 1e-10 and el <= 1e-10
 
 
+def test_c1_fp64_error_against_exact_dense():
+    """The method's own error at the plain FP64 workload: the GPU's X~ against
+    the exact K^-1 A (dense Cholesky of K_f + sigma2 I on the host). The GPU
+    path equals the oracle to 1e-10, so its error against the exact solve is
+    the oracle's, stored in tests/golden/exact_dense_reference.txt."""
+    from conftest import read_golden
+    from oracle import kernels as okr
+
+    gold = {k: float(v) for k, v in read_golden("exact_dense_reference.txt")}
+    dev = device()
+    w = W.WORKLOADS["C1"]
+    x, A, om_np, _, Y, Q, R, sol = _forward(w, "f64", dev)
+    xd = x.astype(np.float64)
+    k = okr.kernel_matrix(w.kernel, xd, xd, w.ell, w.s) + w.sigma2 * np.eye(w.n)
+    lo = np.linalg.cholesky(k)
+    xe = np.linalg.solve(lo.T, np.linalg.solve(lo, A.astype(np.float64)))
+    err = float(np.linalg.norm(sol.X.cpu().numpy() - xe) / np.linalg.norm(xe))
+    ld_ex = 2.0 * float(np.sum(np.log(np.diag(lo))))
+    note(f"  X rel error vs exact dense {err:.6e} (method, oracle: {gold['c1_method_x_relerr']:.6e}); "
+         f"log|K~| {sol.logdet.item():.10e} vs exact log|K| {ld_ex:.10e}")
+    assert abs(err - gold["c1_method_x_relerr"]) <= 1e-8
+    assert abs(sol.logdet.item() - gold["c1_method_logdet"]) <= 1e-10 * abs(gold["c1_method_logdet"])
+
+
 def test_c1_fp64_stagewise_core():
     # the oracle's core and apply fed the GPU's own Q, R (promoted) must agree closely
     dev = device()

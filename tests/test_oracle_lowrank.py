@@ -114,3 +114,28 @@ def test_shift_beyond_spectrum_reports_not_pd():
     lam_min = np.linalg.eigvalsh(c["C"]).min()
     bad = lowrank.core(q, r, om, w.sigma2, nu=w.sigma2 + lam_min + 1.0)
     assert bad["info"] > 0
+
+
+def test_exact_dense_reference_c1_is_reproducible():
+    """The stored exact-dense quantities of the plain FP64 workload
+    (tests/golden/exact_dense_reference.txt, written by make_exact_reference.py)
+    are reproduced here: the exact K^-1 A solves K X = A to round-off, and the
+    method's X~ is a rank-64 approximation whose error against it (about 12%
+    at sigma2 = 1e-4, Sec. 3.1) is a property of the method, not of a path."""
+    from conftest import read_golden
+
+    gold = {k: float(v) for k, v in read_golden("exact_dense_reference.txt")}
+    w = W.WORKLOADS["C1"]
+    x = W.points(w).astype(np.float64)
+    a = W.rhs(w).astype(np.float64)
+    k = kernels.kernel_matrix(w.kernel, x, x, w.ell, w.s) + w.sigma2 * np.eye(w.n)
+    lo = np.linalg.cholesky(k)
+    xe = np.linalg.solve(lo.T, np.linalg.solve(lo, a))
+    assert np.linalg.norm(k @ xe - a) <= 1e-6 * np.linalg.norm(k) * np.linalg.norm(xe)
+    assert abs(np.linalg.norm(xe) - gold["c1_x_exact_fro"]) <= 1e-8 * gold["c1_x_exact_fro"]
+    ld = 2.0 * float(np.sum(np.log(np.diag(lo))))
+    assert abs(ld - gold["c1_logdet_exact"]) <= 1e-10 * abs(ld)
+    fwd = grad.forward(W.points(w), w.kernel, w.ell, w.s, w.sigma2, _srht(w), W.rhs(w), w.leaf_rows)
+    err = np.linalg.norm(fwd["X"] - xe) / np.linalg.norm(xe)
+    assert abs(err - gold["c1_method_x_relerr"]) <= 1e-6 * err
+    assert 0.0 < err < 1.0
