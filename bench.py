@@ -155,10 +155,50 @@ def srht_sketch_rates(name: str, reps: int, torch, api, W, dev) -> dict:
             "alu_frac": adds / (ms / 1e3) / (PEAKS["fp32_add_tops"] * 1e12)}
 
 
+def _exact_c4():
+    """Exact dense log-likelihood and gradient at the log-likelihood workload,
+    as stored by tests/golden/make_exact_reference.py (None if absent)."""
+    path = os.path.join(ROOT, "tests", "golden", "exact_dense_reference.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split()
+                vals[k] = float(v)
+    return vals
+
+
+def c1_error_vs_exact(torch, api, W, dev) -> dict:
+    """The plain FP64 workload (n = 2048, SE, SRHT d = 64): the GPU's X~ against
+    the exact K^-1 A, from a dense float64 Cholesky of K_f + sigma2 I on the
+    host (torch CPU), and log|K~| against log|K|."""
+    w = W.WORKLOADS["C1"]
+    xnp = W.points(w)
+    A = W.rhs(w)
+    signs, cols = W.srht_draw(w)
+    om = api.Omega.srht(signs, cols, dev)
+    fw = api.forward(torch.from_numpy(xnp).to(dev), api.Hyper(w.kernel, w.ell, w.s), om, "f64", w.sigma2,
+                     torch.from_numpy(A).to(dev, torch.float64), w.leaf_rows)
+    xt = torch.from_numpy(xnp).double()
+    r2 = torch.cdist(xt, xt).square()
+    k = w.s ** 2 * torch.exp(-r2 / (2.0 * w.ell ** 2)) + w.sigma2 * torch.eye(w.n, dtype=torch.float64)
+    lo = torch.linalg.cholesky(k)
+    xe = torch.cholesky_solve(torch.from_numpy(A).double(), lo)
+    xg = fw.sol.X.cpu()
+    return {"workload": f"C1: n={w.n} {w.kernel} ell={w.ell} sigma2={w.sigma2} SRHT d={w.d}, FP64 path",
+            "x_rel_err_vs_exact": float((xg - xe).norm() / xe.norm()),
+            "logdet": fw.sol.logdet.item(), "logdet_exact": float(2.0 * torch.log(torch.diagonal(lo)).sum())}
+
+
 def loglik_timing(torch, api, W, dev) -> dict:
     """The log-likelihood workload (n = 32768, d = 256): forward + log-likelihood
-    and the hyperparameter backward, FP64 (nu = 0) and FP32 with the
-    stabilising shift nu = sigma2 / 10 (at nu = 0 its float32 core is indefinite)."""
+    and the hyperparameter backward, FP64 (nu = 0) and FP32 with a stabilising
+    shift (at nu = 0 its float32 core is indefinite): nu = sigma2 / 10 and
+    sigma2 / 300. Each path's log-likelihood and gradient are compared with the
+    exact dense values (the shift is a change of method, so its error against
+    them grows with nu)."""
     w = W.WORKLOADS["C4"]
     xnp = W.points(w)
     x = torch.from_numpy(xnp).to(dev)
@@ -167,25 +207,37 @@ def loglik_timing(torch, api, W, dev) -> dict:
     om = api.Omega.srht(signs, cols, dev)
     hyp = api.Hyper(w.kernel, w.ell, w.s)
     stream = torch.cuda.current_stream(dev)
+    exact = _exact_c4()
     out = {"workload": f"C4: n={w.n} D={w.D} {w.kernel} SRHT d={w.d} (targets: random-Fourier-feature GP draw)"}
-    for prec, nu in (("f64", 0.0), ("f32", 0.1 * w.sigma2)):
+    for key, prec, nu in (("f64", "f64", 0.0), ("f32", "f32", 0.1 * w.sigma2),
+                          ("f32_small_shift", "f32", w.sigma2 / 300.0)):
         dt = torch.float64 if prec == "f64" else torch.float32
         y = torch.from_numpy(yv).to(dev, dt).reshape(-1, 1)
         state = {}
 
         def fwd():
             fw = api.forward(x, hyp, om, prec, w.sigma2, y, w.leaf_rows, nu=nu, want_yprime=True)
-            api.loglik(y, fw.sol.X, fw.sol.logdet, fw.sol.info, prec)
+            state["ll"] = api.loglik(y, fw.sol.X, fw.sol.logdet, fw.sol.info, prec)
             state["fw"] = fw
 
         def bwd():
             fw = state["fw"]
-            api.backward(x, hyp, om, prec, fw.sol, fw.Q, w.sigma2, 0, y, Yprime=fw.Yprime, R=fw.R, nu=nu)
+            state["g"], _ = api.backward(x, hyp, om, prec, fw.sol, fw.Q, w.sigma2, 0, y, Yprime=fw.Yprime, R=fw.R,
+                                         nu=nu)
 
         f_ms = _event_ms(fwd, 3, torch, stream)
         b_ms = _event_ms(bwd, 3, torch, stream)
-        out[prec] = {"nu": nu, "forward_loglik_ms": f_ms, "backward_ms": b_ms,
-                     "info": int(state["fw"].sol.info.item())}
+        info = int(state["fw"].sol.info.item())
+        row = {"nu": nu, "forward_loglik_ms": f_ms, "backward_ms": b_ms, "info": info}
+        if info == 0:
+            ll = float(state["ll"].item())
+            g = [float(v) for v in state["g"].cpu()]
+            row.update({"loglik": ll, "grad": g})
+            if exact is not None:
+                row["loglik_err_vs_exact"] = ll - exact["c4_loglik_exact"]
+                row["grad_err_vs_exact"] = [g[i] - exact[k] for i, k in enumerate(
+                    ("c4_grad_logell_exact", "c4_grad_logs_exact", "c4_grad_logsigma2_exact"))]
+        out[key] = row
     return out
 
 
@@ -380,6 +432,7 @@ def main() -> int:
         result["srht"] = [srht_sketch_rates("C2", 3, torch, api, W, dev),
                           srht_sketch_rates("C5", 1, torch, api, W, dev)]
         result["loglik"] = loglik_timing(torch, api, W, dev)
+        result["c1_exact"] = c1_error_vs_exact(torch, api, W, dev)
 
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w, x, om_np, flops["sketch"])

@@ -12,6 +12,8 @@ It is written to be read against the paper (Banerjee, Vogelstein, Dunson,
 * ``kernels``  squared-exponential and Matern covariances (Sec. 5.1, Sec. 4.1).
 * ``srht``     the Walsh-Hadamard matrix by the Sylvester recursion and the
                structured random matrix Omega = c R T P (Def. 1, Sec. 3.2).
+* ``transforms`` the discrete cosine and Hartley forms of the same
+               structured Omega, for any n (Sec. 3.2; Sec. 5, Table 3).
 * ``sketch``   Y = (K_f + nu I) Omega (Sec. 3.1-3.2).
 * ``qr``       Householder QR and the binary-tree blocked QR, Eq. (1)-(4)
                (Sec. 3.3).
@@ -29,4 +31,4 @@ Parity pins: every function is pinned by ``tests/test_oracle_*.py`` against
 values the paper prints (Tables 1-2), closed forms, library routines and
 brute force on small inputs; the module headers list the pins.
 """
-from . import kernels, srht, sketch, qr, lowrank, grad  # noqa: F401
+from . import kernels, srht, transforms, sketch, qr, lowrank, grad  # noqa: F401

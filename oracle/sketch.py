@@ -9,6 +9,7 @@ any subset of rows can be computed on its own (used for sampled parity).
 
 Omega is described by a small dict:
   {"kind": "srht", "signs": int8[n], "cols": int32[d]}
+  {"kind": "dct" or "dht", "signs": int8[n], "cols": int32[d]}  (transforms.py)
   {"kind": "gauss", "omega_t": float[d, n]}   (Omega stored transposed)
 
 Precision model (for the bf16 matrix-core paths): ``k_round="bf16"`` rounds each
@@ -26,13 +27,15 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import kernels, srht
+from . import kernels, srht, transforms
 
 
 def omega_dense(omega: dict, n: int) -> np.ndarray:
     """Explicit n x d Omega (small n only)."""
     if omega["kind"] == "srht":
         return srht.srht_dense(omega["signs"], omega["cols"])
+    if omega["kind"] in transforms.KINDS:
+        return transforms.omega_dense(omega["kind"], omega["signs"], omega["cols"])
     return np.asarray(omega["omega_t"], dtype=np.float64).T.copy()
 
 
@@ -41,11 +44,13 @@ def omega_rows(omega: dict, rows: np.ndarray) -> np.ndarray:
     rows = np.asarray(rows, dtype=np.int64)
     if omega["kind"] == "srht":
         return srht.entries(omega["signs"], omega["cols"], rows)
+    if omega["kind"] in transforms.KINDS:
+        return transforms.omega_entries(omega["kind"], omega["signs"], omega["cols"], rows)
     return np.asarray(omega["omega_t"], dtype=np.float64)[:, rows].T.copy()
 
 
 def omega_d(omega: dict) -> int:
-    if omega["kind"] == "srht":
+    if omega["kind"] == "srht" or omega["kind"] in transforms.KINDS:
         return int(np.asarray(omega["cols"]).shape[0])
     return int(np.asarray(omega["omega_t"]).shape[0])
 
@@ -66,6 +71,8 @@ def round_to_bf16x2(a: np.ndarray) -> np.ndarray:
 def _right_apply(kblock: np.ndarray, omega: dict) -> np.ndarray:
     if omega["kind"] == "srht":
         return srht.right_apply(kblock, omega["signs"], omega["cols"])
+    if omega["kind"] in transforms.KINDS:
+        return transforms.right_apply(kblock, omega["kind"], omega["signs"], omega["cols"])
     return kblock @ np.asarray(omega["omega_t"], dtype=np.float64).T
 
 
@@ -108,4 +115,6 @@ def omega_t_apply(omega: dict, q: np.ndarray) -> np.ndarray:
     """Omega^T Q (d x r)."""
     if omega["kind"] == "srht":
         return srht.left_apply_t(q, omega["signs"], omega["cols"])
+    if omega["kind"] in transforms.KINDS:
+        return transforms.left_apply_t(q, omega["kind"], omega["signs"], omega["cols"])
     return np.asarray(omega["omega_t"], dtype=np.float64) @ np.asarray(q, dtype=np.float64)
