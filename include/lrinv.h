@@ -84,7 +84,8 @@ typedef struct {
  *       signs: device int8[n] (negative = -1, otherwise +1);
  *       cols:  device int32[d], distinct, in [0, n) (see lr_check_srht_cols).
  *       n must be a power of two.
- *   LR_OMEGA_GAUSS (dense, e.g. i.i.d. N(0, 1/d), Sec. 3.1):
+ *   LR_OMEGA_GAUSS (any dense Omega: i.i.d. N(0, 1/d), Sec. 3.1, or a structured
+ *       transform written out by lr_structured_omega):
  *       dense_t: device, Omega TRANSPOSED, d rows of length >= n with leading
  *       dimension ld (elements, ld >= n, ld % 8 == 0, 16-byte aligned base),
  *       element type double (F64), float (F32) or bfloat16 bits (BF16, BF16X2). */
@@ -97,6 +98,30 @@ typedef struct {
   const int32_t *cols; /* SRHT only */
   const void *dense_t; /* GAUSS only */
 } lr_omega;
+
+/* ---------------------------------------------------------------- structured Omega, written out
+ * Omega[j,k] = signs[j] T[j, cols[k]] for a fast orthogonal transform T
+ * (Def. 1 of Sec. 3.2; the paper's experiments use the cosine and Hartley
+ * forms, Sec. 5 and Table 3), written as the dense TRANSPOSED Omega of
+ * LR_OMEGA_GAUSS so that every entry point takes it as a dense Omega:
+ *   LR_TRANSFORM_DCT  orthonormal DCT-II: T[j,p] = a_p cos(pi (2j+1) p / (2n)),
+ *                     a_0 = n^{-1/2}, a_p = (2/n)^{1/2}; any n.
+ *   LR_TRANSFORM_DHT  discrete Hartley: T[j,p] = n^{-1/2} (cos + sin)(2 pi j p / n); any n.
+ *   LR_TRANSFORM_WHT  Walsh-Hadamard: T[j,p] = n^{-1/2} (-1)^popcount(j & p); n a power of two.
+ * T is orthogonal, so the columns of Omega are orthonormal.
+ *   signs    device int8[n] (negative = -1, otherwise +1).
+ *   cols     device int32[d], distinct, in [0, n) (see lr_check_srht_cols); any
+ *            value is memory-safe (it only enters the formula, reduced mod n).
+ *   prec     element type written: double (F64), float (F32), bfloat16 bits
+ *            (BF16, BF16X2). Each entry is evaluated in float64 with the angle
+ *            reduced exactly in integers, then rounded to nearest even.
+ *   omega_t  device output, d rows of leading dimension ld (elements; ld >= n,
+ *            ld % 8 == 0, 16-byte aligned base); columns n .. ld-1 are zeroed.
+ * Errors: LR_ERR_ARG (transform, prec, NULL pointer), LR_ERR_SHAPE (n, d, ld),
+ * LR_ERR_NOT_POW2 (WHT with n not a power of two). No workspace. */
+typedef enum { LR_TRANSFORM_DCT = 0, LR_TRANSFORM_DHT = 1, LR_TRANSFORM_WHT = 2 } lr_transform;
+lr_status lr_structured_omega(void *stream, int32_t transform, int64_t n, int32_t d, const int8_t *signs,
+                              const int32_t *cols, int32_t prec, void *omega_t, int64_t ld);
 
 /* Host-side check of SRHT column indices (host pointer): LR_OK when the d entries
  * are distinct and in [0, n), LR_ERR_ARG otherwise. Device kernels are memory-safe
@@ -224,7 +249,8 @@ lr_status lr_backward(void *stream, int64_t n, int32_t D, const float *X, const 
 const char *lr_status_string(int32_t status);
 
 /* ABI version: (major << 16) | minor. 2.0: lr_backward takes the forward's
- * right-hand side A instead of its solution, and R and the shift nu. */
+ * right-hand side A instead of its solution, and R and the shift nu.
+ * 2.1: lr_structured_omega. */
 int32_t lr_version(void);
 
 #ifdef __cplusplus

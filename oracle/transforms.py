@@ -16,7 +16,8 @@ exactly as for Walsh-Hadamard. D is the Rademacher diagonal and P the d
 columns (drawn without replacement, sorted), as in srht.py.
 
 Entries come from the formulas above with the angle reduced exactly in
-integers ((2j + 1) p mod 4n, j p mod n) before the float64 cosine and sine.
+integers to the first octant before the float64 cosine or sine (the Hartley
+entry as sqrt(2) cos(t - pi/4)), so exact zeros stay zero.
 The products K Omega and Omega^T Q use fast transforms (scipy.fft) along the
 transform axis, then pick the columns P.
 
@@ -33,18 +34,31 @@ import scipy.fft
 KINDS = ("dct", "dht")
 
 
+def cos_pi_ratio(k: np.ndarray, big_n: int) -> np.ndarray:
+    """cos(pi k / N) for integers k, with the quadrant reduced in integers
+    (cos(-a) = cos a, cos(pi - a) = -cos a, cos a = sin(pi/2 - a)), so the
+    float64 cosine or sine only sees an angle in [0, pi/4] and zeros come out
+    exactly zero."""
+    k = np.mod(np.asarray(k, dtype=np.int64), 2 * big_n)   # [0, 2N)
+    k = np.where(k > big_n, 2 * big_n - k, k)               # [0, N]
+    sign = np.where(2 * k > big_n, -1.0, 1.0)
+    k = np.where(2 * k > big_n, big_n - k, k)               # [0, N/2]
+    use_sin = 4 * k > big_n
+    return sign * np.where(use_sin, np.sin(np.pi * (big_n - 2 * k) / (2.0 * big_n)),
+                           np.cos(np.pi * k / float(big_n)))
+
+
 def transform_entries(kind: str, n: int, rows: np.ndarray, cols: np.ndarray) -> np.ndarray:
     """T[rows, cols] (float64) from the closed forms, angles reduced in integers."""
     j = np.asarray(rows, dtype=np.int64)[:, None]
     p = np.asarray(cols, dtype=np.int64)[None, :]
     if kind == "dct":
-        m = ((2 * j + 1) * p) % (4 * n)                      # angle = pi m / (2n)
         a = np.where(p == 0, np.sqrt(1.0 / n), np.sqrt(2.0 / n))
-        return a * np.cos(np.pi * m / (2.0 * n))
+        return a * cos_pi_ratio((2 * j + 1) * p, 2 * n)          # cos(pi (2j+1) p / (2n))
     if kind == "dht":
-        m = (j * p) % n                                       # angle = 2 pi m / n
-        t = 2.0 * np.pi * m / n
-        return (np.cos(t) + np.sin(t)) / np.sqrt(n)
+        # cas t = cos t + sin t = sqrt(2) cos(t - pi/4), t = 2 pi m / n
+        m = (j * p) % n
+        return np.sqrt(2.0) * cos_pi_ratio(8 * m - n, 4 * n) / np.sqrt(n)
     raise ValueError(f"unknown transform {kind!r}")
 
 

@@ -16,6 +16,8 @@ NOALLOC_SCRATCH_BYTES = 32 << 20
 LR_KERNEL_SE, LR_KERNEL_MATERN32 = 0, 1
 LR_OMEGA_SRHT, LR_OMEGA_GAUSS = 0, 1
 LR_PREC_F64, LR_PREC_F32, LR_PREC_BF16, LR_PREC_BF16X2 = 0, 1, 2, 3
+LR_TRANSFORM_DCT, LR_TRANSFORM_DHT, LR_TRANSFORM_WHT = 0, 1, 2
+TRANSFORMS = {"dct": LR_TRANSFORM_DCT, "dht": LR_TRANSFORM_DHT, "wht": LR_TRANSFORM_WHT}
 
 PRECS = {"f64": LR_PREC_F64, "f32": LR_PREC_F32, "bf16": LR_PREC_BF16, "bf16x2": LR_PREC_BF16X2}
 KERNELS = {"se": LR_KERNEL_SE, "matern32": LR_KERNEL_MATERN32}
@@ -42,6 +44,7 @@ _SIGS = {
     "lr_version": (c_i32, []),
     "lr_status_string": (ctypes.c_char_p, [c_i32]),
     "lr_check_srht_cols": (c_i32, [c_vp, c_i32, c_i64]),
+    "lr_structured_omega": (c_i32, [c_vp, c_i32, c_i64, c_i32, c_vp, c_vp, c_i32, c_vp, c_i64]),
     "lr_sketch_workspace_bytes": (c_sz, [c_i64, c_i32, c_i32, c_i32]),
     "lr_sketch": (c_i32, [c_vp, c_i64, c_i32, c_vp, ctypes.POINTER(LrHyper), ctypes.POINTER(LrOmega), c_dbl, c_i32,
                           c_vp, c_vp, c_vp, c_sz]),

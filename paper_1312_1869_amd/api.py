@@ -77,6 +77,24 @@ class Omega:
                      cols=torch.from_numpy(cols).to(device))
 
     @staticmethod
+    def structured(transform: str, signs: np.ndarray, cols: np.ndarray, prec: str, device) -> "Omega":
+        """Omega = D T P for T the orthonormal DCT-II ("dct"), the discrete
+        Hartley transform ("dht") or Walsh-Hadamard ("wht"), written out on the
+        device by lr_structured_omega as a dense transposed Omega (d x ld, ld =
+        n rounded up to 64) in the element type of ``prec``."""
+        cols = np.ascontiguousarray(cols, dtype=np.int32)
+        n, d = int(signs.shape[0]), int(cols.shape[0])
+        L.check(L.lib().lr_check_srht_cols(cols.ctypes.data_as(ctypes.c_void_p), d, n), "lr_check_srht_cols")
+        ld = (n + 63) // 64 * 64
+        dt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "bf16x2": torch.bfloat16}[prec]
+        sg = torch.from_numpy(np.ascontiguousarray(signs, dtype=np.int8)).to(device)
+        cl = torch.from_numpy(cols).to(device)
+        dense = torch.empty((d, ld), dtype=dt, device=device)
+        L.check(L.lib().lr_structured_omega(_stream(device), L.TRANSFORMS[transform], n, d, _p(sg), _p(cl),
+                                            L.PRECS[prec], _p(dense), ld), "lr_structured_omega")
+        return Omega("gauss", n, d, dense_t=dense, ld=ld)
+
+    @staticmethod
     def gauss(omega_t: np.ndarray, prec: str, device) -> "Omega":
         """Omega given transposed (d x n); stored d x ld with ld = n rounded up to 64."""
         d, n = omega_t.shape

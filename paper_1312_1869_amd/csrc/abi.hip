@@ -323,7 +323,7 @@ TnOperand f64_operand(const double* p, int64_t ld) {
 
 extern "C" {
 
-int32_t lr_version(void) { return (2 << 16) | 0; }
+int32_t lr_version(void) { return (2 << 16) | 1; }
 
 const char* lr_status_string(int32_t s) {
   switch (s) {
@@ -347,6 +347,22 @@ lr_status lr_check_srht_cols(const int32_t* cols, int32_t d, int64_t n) {
     for (int32_t j = 0; j < i; ++j)
       if (cols[j] == cols[i]) return LR_ERR_ARG;
   }
+  return LR_OK;
+}
+
+lr_status lr_structured_omega(void* stream, int32_t transform, int64_t n, int32_t d, const int8_t* signs,
+                              const int32_t* cols, int32_t prec, void* omega_t, int64_t ld) {
+  if (transform != LR_TRANSFORM_DCT && transform != LR_TRANSFORM_DHT && transform != LR_TRANSFORM_WHT)
+    return LR_ERR_ARG;
+  if (!valid_prec(prec)) return LR_ERR_ARG;
+  lr_status s = check_sizes(n, d);
+  if (s != LR_OK) return s;
+  if (n > ((int64_t)1 << 30)) return LR_ERR_SHAPE;  // (2j+1) p stays below 2^62
+  if (ld < n || ld % 8 != 0) return LR_ERR_SHAPE;
+  if (transform == LR_TRANSFORM_WHT && (n & (n - 1)) != 0) return LR_ERR_NOT_POW2;
+  if (signs == nullptr || cols == nullptr || omega_t == nullptr || !aligned(omega_t, 16)) return LR_ERR_ARG;
+  LR_HIP(launch_structured_omega(static_cast<hipStream_t>(stream), transform, n, d, signs, cols, prec, omega_t, ld,
+                                 num_cu_current()));
   return LR_OK;
 }
 

@@ -17,6 +17,9 @@ hipError_t launch_sketch_srht(hipStream_t st, int kernel, int D, const T* pts, c
 hipError_t launch_sketch_dense(hipStream_t st, int prec, int kernel, int D, const void* pts, const void* omt,
                                int64_t ld, int64_t n, int d, double scale_out, double nu, void* Y, bool deriv,
                                const void* frag, int num_cu);
+// Dense transposed Omega of a structured transform (lr_structured_omega).
+hipError_t launch_structured_omega(hipStream_t st, int transform, int64_t n, int d, const int8_t* signs,
+                                   const int32_t* cols, int prec, void* out, int64_t ld, int num_cu);
 // Omega (bf16, d x ld transposed) in matrix-core fragment order for the bf16
 // sketch with D <= 3; omega_frag_bytes gives the size of that copy.
 hipError_t launch_omega_frag(hipStream_t st, const void* omt, int64_t ld, int64_t n, int d, void* frag);

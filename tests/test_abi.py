@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_version_and_status_strings():
     lib = L.lib()
-    assert lib.lr_version() >> 16 == 2
+    assert lib.lr_version() >> 16 == 2 and lib.lr_version() & 0xFFFF >= 1
     assert lib.lr_status_string(L.LR_ERR_NOT_POW2) == b"LR_ERR_NOT_POW2"
     assert lib.lr_status_string(99) == b"LR_UNKNOWN_STATUS"
 
@@ -131,3 +131,19 @@ def test_solve_and_backward_validation():
     assert b(nu=-1e-3) == L.LR_ERR_ARG
     assert b(nu=1e-4, R=None) == L.LR_ERR_ARG     # a shift needs R
     assert lib.lr_loglik(None, 0, L.LR_PREC_F32, FAKE, FAKE, FAKE, None, FAKE) == L.LR_ERR_SHAPE
+
+
+def test_structured_omega_validation():
+    lib = L.lib()
+    so = lambda t=L.LR_TRANSFORM_DCT, n=1000, d=64, prec=L.LR_PREC_F32, ld=1008, out=FAKE, signs=FAKE: \
+        lib.lr_structured_omega(None, t, n, d, signs, FAKE, prec, out, ld)
+    assert so(t=3) == L.LR_ERR_ARG
+    assert so(prec=9) == L.LR_ERR_ARG
+    assert so(ld=1001) == L.LR_ERR_SHAPE          # ld % 8
+    assert so(ld=992) == L.LR_ERR_SHAPE           # ld < n
+    assert so(d=2000, n=4096, ld=4096) == L.LR_ERR_SHAPE  # d > 1024
+    assert so(d=0) == L.LR_ERR_SHAPE
+    assert so(t=L.LR_TRANSFORM_WHT) == L.LR_ERR_NOT_POW2  # n = 1000
+    assert so(out=None) == L.LR_ERR_ARG
+    assert so(out=ctypes.c_void_p(0x10008)) == L.LR_ERR_ARG  # not 16-byte aligned
+    assert so(signs=None) == L.LR_ERR_ARG

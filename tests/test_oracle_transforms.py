@@ -119,3 +119,14 @@ def test_method_with_structured_omega_matches_dense_definition(kind):
     out = lowrank.solve(q, r, om, sigma2, a)
     x_true = np.linalg.solve(kf + sigma2 * np.eye(w.n), a)
     np.testing.assert_allclose(out["X"], x_true, rtol=0, atol=1e-6 * np.abs(x_true).max())
+
+
+def test_cos_pi_ratio_quadrants_and_exact_zeros():
+    big_n = 12
+    k = np.arange(-30, 31)
+    np.testing.assert_allclose(transforms.cos_pi_ratio(k, big_n), np.cos(np.pi * k / big_n), rtol=0, atol=4e-15)
+    assert np.all(transforms.cos_pi_ratio(np.array([6, 18, -6, 30]), big_n) == 0.0)
+    # the cosine / Hartley zeros of the transforms are exact
+    n = 8
+    assert transforms.transform_entries("dht", n, np.array([3]), np.array([1]))[0, 0] == 0.0  # cas(3 pi / 4)
+    assert transforms.transform_entries("dct", 2, np.array([0]), np.array([2]))[0, 0] == 0.0  # cos(pi / 2)
