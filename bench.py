@@ -155,6 +155,31 @@ def srht_sketch_rates(name: str, reps: int, torch, api, W, dev) -> dict:
             "alu_frac": adds / (ms / 1e3) / (PEAKS["fp32_add_tops"] * 1e12)}
 
 
+def structured_rates(torch, api, W, dev) -> dict:
+    """Cosine / Hartley Omega (any n): the C2 shape with n = 60000 (not a power
+    of two, so Walsh-Hadamard does not apply): writing Omega out, the FP32 and
+    bf16 dense sketches of it, and the FP32 forward (sketch, TSQR, solve)."""
+    w = W.small(W.WORKLOADS["C2"], 60000)
+    xnp = W.points(w)
+    x = torch.from_numpy(xnp).to(dev)
+    A = torch.from_numpy(W.rhs(w)).to(dev, torch.float32)
+    signs, cols = W.srht_draw(w)
+    hyp = api.Hyper(w.kernel, w.ell, w.s)
+    stream = torch.cuda.current_stream(dev)
+    out = {"workload": f"n={w.n} D={w.D} {w.kernel} ell={w.ell} d={w.d} m={w.m} leaf_rows={w.leaf_rows}"}
+    for t in ("dct", "dht"):
+        gen_ms = _event_ms(lambda: api.Omega.structured(t, signs, cols, "f32", dev), 3, torch, stream)
+        om32 = api.Omega.structured(t, signs, cols, "f32", dev)
+        omb = api.Omega.structured(t, signs, cols, "bf16", dev)
+        sk32 = _event_ms(lambda: api.sketch(x, hyp, om32, "f32"), 3, torch, stream)
+        skb = _event_ms(lambda: api.sketch(x, hyp, omb, "bf16"), 3, torch, stream)
+        fw = _event_ms(lambda: api.forward(x, hyp, om32, "f32", w.sigma2, A, w.leaf_rows), 3, torch, stream)
+        out[t] = {"omega_write_ms": gen_ms, "sketch_f32_ms": sk32, "sketch_bf16_ms": skb, "forward_f32_ms": fw,
+                  "sketch_f32_frac_of_fp32_mfma_peak": 2.0 * w.n * w.n * w.d / (sk32 / 1e3) / 1e12
+                  / PEAKS["fp32_tflops"]}
+    return out
+
+
 def _exact_c4():
     """Exact dense log-likelihood and gradient at the log-likelihood workload,
     as stored by tests/golden/make_exact_reference.py (None if absent)."""
@@ -433,6 +458,7 @@ def main() -> int:
                           srht_sketch_rates("C5", 1, torch, api, W, dev)]
         result["loglik"] = loglik_timing(torch, api, W, dev)
         result["c1_exact"] = c1_error_vs_exact(torch, api, W, dev)
+        result["structured_omega"] = structured_rates(torch, api, W, dev)
 
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w, x, om_np, flops["sketch"])
