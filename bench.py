@@ -180,6 +180,27 @@ def structured_rates(torch, api, W, dev) -> dict:
     return out
 
 
+def grid_rates(torch, api, W, dev, g: int = 16) -> dict:
+    """A grid of g range parameters at the log-likelihood workload (FP32, SRHT
+    d = 256, the stabilising shift sigma2 / 10): one lr_sketch_grid call against
+    g single sketches, and the whole log-likelihood grid."""
+    w = W.WORKLOADS["C4"]
+    xnp = W.points(w)
+    x = torch.from_numpy(xnp).to(dev)
+    yv = torch.from_numpy(W.gp_targets(w, xnp)).to(dev)
+    signs, cols = W.srht_draw(w)
+    om = api.Omega.srht(signs, cols, dev)
+    hyps = [api.Hyper(w.kernel, float(e), w.s) for e in np.linspace(0.5 * w.ell, 2.0 * w.ell, g)]
+    nu = 0.1 * w.sigma2
+    stream = torch.cuda.current_stream(dev)
+    grid_ms = _event_ms(lambda: api.sketch_grid(x, hyps, om, "f32", nu=nu), 3, torch, stream)
+    single_ms = _event_ms(lambda: [api.sketch(x, h, om, "f32", nu=nu) for h in hyps], 3, torch, stream)
+    ll_ms = _event_ms(lambda: api.loglik_grid(x, hyps, [w.sigma2] * g, om, "f32", yv, w.leaf_rows, nu=nu), 2,
+                      torch, stream)
+    return {"workload": f"C4 shape, FP32, {g} values of ell in [{0.5 * w.ell}, {2.0 * w.ell}], nu = sigma2/10",
+            "sketch_grid_ms": grid_ms, "single_sketches_ms": single_ms, "loglik_grid_ms": ll_ms}
+
+
 def _exact_c4():
     """Exact dense log-likelihood and gradient at the log-likelihood workload,
     as stored by tests/golden/make_exact_reference.py (None if absent)."""
@@ -459,6 +480,7 @@ def main() -> int:
         result["loglik"] = loglik_timing(torch, api, W, dev)
         result["c1_exact"] = c1_error_vs_exact(torch, api, W, dev)
         result["structured_omega"] = structured_rates(torch, api, W, dev)
+        result["hyperparameter_grid"] = grid_rates(torch, api, W, dev)
 
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w, x, om_np, flops["sketch"])

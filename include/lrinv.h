@@ -164,6 +164,22 @@ lr_status lr_sketch(void *stream, int64_t n, int32_t D, const float *X, const lr
 lr_status lr_sketch_noalloc(void *stream, int64_t n, int32_t D, const float *X, const lr_hyper *hyp,
                             const lr_omega *omega, double nu, int32_t prec, void *Y, void *Yprime);
 
+/* ---------------------------------------------------------------- hyperparameter grid
+ * Sketches for a batch of ntheta kernels that share the points, the kernel
+ * kind and Omega and differ in ell and s (the grids over the range parameter
+ * of Sec. 5.2): Y_g = (K_f(theta_g) + nu I) Omega for g < ntheta, written to
+ * Y + g n d. With an SRHT Omega one pass serves two kernels: each point load
+ * and squared distance is shared, and each kernel runs its own transform. A
+ * dense Omega runs the single-kernel sketch once per g.
+ *   hyps    host array of ntheta lr_hyper, all with the same kernel kind
+ *           (LR_ERR_ARG otherwise); 1 <= ntheta <= 4096.
+ *   Y       device real ntheta x n x d (row-major per g).
+ * Precisions as lr_sketch; no derivative output (lr_backward recomputes it).
+ * Workspace: lr_sketch_grid_workspace_bytes, the same as lr_sketch's. */
+size_t lr_sketch_grid_workspace_bytes(int64_t n, int32_t D, int32_t d, int32_t prec);
+lr_status lr_sketch_grid(void *stream, int64_t n, int32_t D, const float *X, int32_t ntheta, const lr_hyper *hyps,
+                         const lr_omega *omega, double nu, int32_t prec, void *Y, void *ws, size_t ws_bytes);
+
 /* ---------------------------------------------------------------- tsqr
  * Binary-tree blocked QR of the n x d matrix Y (Sec. 3.3, Eq. 1-4).
  *   Rows are split into leaves of leaf_rows rows (the last leaf may be shorter
@@ -250,7 +266,7 @@ const char *lr_status_string(int32_t status);
 
 /* ABI version: (major << 16) | minor. 2.0: lr_backward takes the forward's
  * right-hand side A instead of its solution, and R and the shift nu.
- * 2.1: lr_structured_omega. */
+ * 2.1: lr_structured_omega, lr_sketch_grid. */
 int32_t lr_version(void);
 
 #ifdef __cplusplus

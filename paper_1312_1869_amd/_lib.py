@@ -50,6 +50,9 @@ _SIGS = {
                           c_vp, c_vp, c_vp, c_sz]),
     "lr_sketch_noalloc": (c_i32, [c_vp, c_i64, c_i32, c_vp, ctypes.POINTER(LrHyper), ctypes.POINTER(LrOmega), c_dbl,
                                   c_i32, c_vp, c_vp]),
+    "lr_sketch_grid_workspace_bytes": (c_sz, [c_i64, c_i32, c_i32, c_i32]),
+    "lr_sketch_grid": (c_i32, [c_vp, c_i64, c_i32, c_vp, c_i32, c_vp, ctypes.POINTER(LrOmega), c_dbl, c_i32, c_vp,
+                               c_vp, c_sz]),
     "lr_tsqr_workspace_bytes": (c_sz, [c_i64, c_i32, c_i32, c_i32]),
     "lr_tsqr": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_sz]),
     "lr_lowrank_solve_workspace_bytes": (c_sz, [c_i64, c_i32, c_i32, c_i32]),

@@ -134,6 +134,39 @@ def sketch(X: torch.Tensor, hyper: Hyper, omega: Omega, prec: str, nu: float = 0
     return Y, Yp
 
 
+def sketch_grid(X: torch.Tensor, hypers: list, omega: Omega, prec: str, nu: float = 0.0) -> torch.Tensor:
+    """Y_g = (K_f(hypers[g]) + nu I) Omega for every g, one lr_sketch_grid call:
+    returns a (G, n, d) tensor."""
+    if X.dtype != torch.float32 or not X.is_contiguous():
+        raise ValueError("points must be contiguous float32")
+    n, D = X.shape
+    g = len(hypers)
+    hs = (L.LrHyper * g)(*[h.struct() for h in hypers])
+    Y = torch.empty((g, n, omega.d), dtype=real_dtype(prec), device=X.device)
+    lib = L.lib()
+    ws = _Workspace(lib.lr_sketch_grid_workspace_bytes(n, D, omega.d, L.PRECS[prec]), X.device)
+    o = omega.struct()
+    L.check(lib.lr_sketch_grid(_stream(X.device), n, D, _p(X), g, ctypes.cast(hs, ctypes.c_void_p),
+                               ctypes.byref(o), float(nu), L.PRECS[prec], _p(Y), ws.ptr, ws.nbytes), "lr_sketch_grid")
+    return Y
+
+
+def loglik_grid(X: torch.Tensor, hypers: list, sigma2s: list, omega: Omega, prec: str, y: torch.Tensor,
+                leaf_rows: int, nu: float = 0.0) -> torch.Tensor:
+    """Approximate log-likelihoods at a grid of hyperparameters (hypers[g],
+    sigma2s[g]): one batched sketch, then the blocked QR, the Woodbury solve
+    and lr_loglik per grid point, all on the current stream. Returns a float64
+    tensor of G values (NaN where the core is not positive definite)."""
+    Ys = sketch_grid(X, hypers, omega, prec, nu=nu)
+    out = torch.empty(len(hypers), dtype=torch.float64, device=X.device)
+    yc = y.reshape(-1, 1)
+    for g in range(len(hypers)):
+        Q, R = tsqr(Ys[g], leaf_rows, prec)
+        sol = lowrank_solve(Q, R, omega, prec, float(sigma2s[g]), yc, nu=nu)
+        out[g:g + 1] = loglik(yc, sol.X, sol.logdet, sol.info, prec)
+    return out
+
+
 def tsqr(Y: torch.Tensor, leaf_rows: int, prec: str):
     _check_real(Y, prec, "Y")
     n, d = Y.shape

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <mutex>
+#include <vector>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -385,6 +386,61 @@ lr_status lr_sketch(void* stream, int64_t n, int32_t D, const float* X, const lr
   if (!is_fin(nu) || nu < 0.0) return LR_ERR_ARG;
   if ((s = check_ws(sketch_ws(n, D, omega->d, prec), ws, ws_bytes)) != LR_OK) return s;
   return sketch_impl(static_cast<hipStream_t>(stream), n, D, X, hyp, omega, nu, prec, Y, Yprime, ws);
+}
+
+size_t lr_sketch_grid_workspace_bytes(int64_t n, int32_t D, int32_t d, int32_t prec) {
+  return lr_sketch_workspace_bytes(n, D, d, prec);
+}
+
+lr_status lr_sketch_grid(void* stream, int64_t n, int32_t D, const float* X, int32_t ntheta, const lr_hyper* hyps,
+                         const lr_omega* omega, double nu, int32_t prec, void* Y, void* ws, size_t ws_bytes) {
+  if (!valid_prec(prec)) return LR_ERR_ARG;
+  if (D < 1 || D > 15) return LR_ERR_SHAPE;
+  if (omega == nullptr || hyps == nullptr || X == nullptr || Y == nullptr) return LR_ERR_ARG;
+  if (ntheta < 1 || ntheta > 4096) return LR_ERR_SHAPE;
+  lr_status s = check_sizes(n, omega->d);
+  if (s != LR_OK) return s;
+  for (int32_t g = 0; g < ntheta; ++g) {
+    if ((s = check_hyper(&hyps[g])) != LR_OK) return s;
+    if (hyps[g].kernel != hyps[0].kernel) return LR_ERR_ARG;
+  }
+  if ((s = check_omega(omega, n, omega->d, prec)) != LR_OK) return s;
+  if (!is_fin(nu) || nu < 0.0) return LR_ERR_ARG;
+  if (prec == LR_PREC_BF16X2 && D > 3) return LR_ERR_UNSUPPORTED;
+  if ((s = check_ws(sketch_ws(n, D, omega->d, prec), ws, ws_bytes)) != LR_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int d = omega->d;
+  const size_t es = prec == LR_PREC_F64 ? sizeof(double) : sizeof(float);
+  if (omega->kind != LR_OMEGA_SRHT) {
+    for (int32_t g = 0; g < ntheta; ++g) {
+      void* yg = static_cast<char*>(Y) + (size_t)g * n * d * es;
+      if ((s = sketch_impl(st, n, D, X, &hyps[g], omega, nu, prec, yg, nullptr, ws)) != LR_OK) return s;
+    }
+    return LR_OK;
+  }
+  // SRHT: points prescaled once for ell = 1; kernel g scales the squared
+  // distance by 1/ell_g^2 and its output by c s_g^2
+  const int PD = point_stride(D);
+  const double c = 1.0 / sqrt((double)n);
+  std::vector<double> a(ntheta), so(ntheta);
+  for (int32_t g = 0; g < ntheta; ++g) {
+    a[g] = 1.0 / (hyps[g].ell * hyps[g].ell);
+    so[g] = c * hyps[g].s * hyps[g].s;
+  }
+  const double scale1 = coord_scale(hyps[0].kernel, 1.0);
+  const int ncu = num_cu_current();
+  if (prec == LR_PREC_F64) {
+    double* pts = static_cast<double*>(ws);
+    LR_HIP(launch_prep_points<double>(st, X, n, D, PD, scale1, omega->signs, pts));
+    LR_HIP(launch_sketch_srht_grid<double>(st, hyps[0].kernel, D, pts, omega->cols, n, d, ntheta, a.data(),
+                                           so.data(), nu * c, static_cast<double*>(Y), ncu));
+  } else {
+    float* pts = static_cast<float*>(ws);
+    LR_HIP(launch_prep_points<float>(st, X, n, D, PD, scale1, omega->signs, pts));
+    LR_HIP(launch_sketch_srht_grid<float>(st, hyps[0].kernel, D, pts, omega->cols, n, d, ntheta, a.data(),
+                                          so.data(), nu * c, static_cast<float*>(Y), ncu));
+  }
+  return LR_OK;
 }
 
 lr_status lr_sketch_noalloc(void* stream, int64_t n, int32_t D, const float* X, const lr_hyper* hyp,

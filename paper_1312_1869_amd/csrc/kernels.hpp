@@ -14,6 +14,13 @@ hipError_t launch_prep_points(hipStream_t st, const float* X, int64_t n, int D, 
 template <typename T>
 hipError_t launch_sketch_srht(hipStream_t st, int kernel, int D, const T* pts, const int32_t* cols, int64_t n,
                               int d, double scale_out, double nu_c, T* Y, T* Yp, int num_cu);
+// SRHT sketches Y_g (g < ntheta, Y_g = Y + g n d) for a batch of kernels that
+// differ in ell and s: points prescaled for ell = 1, squared distances times
+// dist_scale[g] = 1/ell_g^2, outputs times scale_out[g].
+template <typename T>
+hipError_t launch_sketch_srht_grid(hipStream_t st, int kernel, int D, const T* pts, const int32_t* cols, int64_t n,
+                                   int d, int ntheta, const double* dist_scale, const double* scale_out, double nu_c,
+                                   T* Y, int num_cu);
 hipError_t launch_sketch_dense(hipStream_t st, int prec, int kernel, int D, const void* pts, const void* omt,
                                int64_t ld, int64_t n, int d, double scale_out, double nu, void* Y, bool deriv,
                                const void* frag, int num_cu);

@@ -12,6 +12,8 @@
 //    (the fused mode); lane l owns outputs l, l+64, ... Work per row:
 //    n (11 + 1) butterflies/adds + d n / 2048 selections, against the 2 n d of
 //    the dense product the structure avoids (Sec. 1, Sec. 3.2).
+//  * sketch_srht_grid_kernel: the same transform for a batch of
+//    hyperparameters sharing the points' loads and squared distances.
 #include <type_traits>
 
 #include "common.hpp"
@@ -56,6 +58,7 @@ constexpr int kChunk = 2048;        // chunk of j transformed at once
 constexpr int kChunkRegs = kChunk / 64;
 constexpr int kBufWords = 2112;     // per wave: 32 x 65 (transpose) and 64 x 33 (selection) layouts
 constexpr int kLoadGroup = 8;       // point loads issued together
+constexpr int kGridPass = 2;        // hyperparameters per pass of the grid kernel
 
 template <typename T, int N>
 __device__ __forceinline__ void fwht_regs(T (&v)[N]) {
@@ -246,6 +249,165 @@ __global__ __launch_bounds__(256) void sketch_srht_kernel(const T* __restrict__ 
     }
   }
 }
+
+// Grid mode (a batch of hyperparameters, Sec. 5.2's grids over the range
+// parameter): the points are prescaled for ell = 1, so one squared distance
+// per (i, j) serves every hyperparameter g of the pass; kernel g evaluates it
+// at r2 * a_g (a_g = 1/ell_g^2) and runs its own transform accumulation. One
+// row per wave, G hyperparameters per pass; outputs Y_g = Y + g * ystride
+// scaled by so_g = c s_g^2.
+template <typename T>
+struct GridPass {
+  T a[kGridPass];
+  T so[kGridPass];
+  int64_t yoff[kGridPass];
+};
+
+template <typename T, int KERNEL, int PD, int ND, int NQ, int G>
+__global__ __launch_bounds__(256) void sketch_srht_grid_kernel(const T* __restrict__ pts,
+                                                               const int32_t* __restrict__ cols, int64_t n, int d,
+                                                               GridPass<T> gp, T nu_c, T* __restrict__ Y) {
+  __shared__ __align__(16) T smem[4 * kBufWords];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  T* buf = smem + wave * kBufWords;
+  using K = KernelT<T, KERNEL>;
+
+  int pk[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int k = lane + 64 * q;
+    pk[q] = (k < d) ? cols[k] : 0;
+  }
+  const int64_t nchunks = (n + kChunk - 1) / kChunk;
+  const int64_t ngroups = (n + 3) / 4;
+
+  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const int64_t i = grp * 4 + wave;
+    T xi[PD];
+    PointLoad<T, PD>::get(pts + (i < n ? i : n - 1) * PD, xi);
+    T acc[G][NQ];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) acc[g][q] = 0;
+
+    for (int64_t c = 0; c < nchunks; ++c) {
+      const int64_t base = c * kChunk;
+      const int last = (int)(n - base < kChunk ? n - base : kChunk);
+      const T* cpts = pts + base * PD;
+      T v[G][kChunkRegs];
+#pragma unroll
+      for (int r = 0; r < kChunkRegs; ++r) {
+        if (r % kLoadGroup == 0) __builtin_amdgcn_sched_barrier(0);
+        int jl = r * 64 + lane;
+        jl = jl < last ? jl : last;
+        T pj[PD];
+        PointLoad<T, PD>::get(cpts + jl * PD, pj);
+        const T sg = pj[PD - 1];
+        T r2 = 0;
+#pragma unroll
+        for (int t = 0; t < ND; ++t) {
+          const T df = xi[t] - pj[t];
+          r2 = __builtin_fma(df, df, r2);
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) v[g][r] = sg * K::value(r2 * gp.a[g]);
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) srht_chunk_accumulate<T, NQ>(v[g], buf, lane, c, pk, d, acc[g]);
+    }
+    if (i >= n) continue;
+    const T sgi = xi[PD - 1];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      T* out = Y + gp.yoff[g];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int k = lane + 64 * q;
+        if (k < d) {
+          T y = gp.so[g] * acc[g][q];
+          if (nu_c != (T)0) {
+            const unsigned par = __popcll((unsigned long long)i & (unsigned long long)pk[q]) & 1u;
+            y += par ? -nu_c * sgi : nu_c * sgi;
+          }
+          out[i * d + k] = y;
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int KERNEL, int PD, int ND, int NQ, int G>
+static hipError_t launch_srht_grid_impl(hipStream_t st, const T* pts, const int32_t* cols, int64_t n, int d,
+                                        const GridPass<T>& gp, double nu_c, T* Y, int num_cu) {
+  auto kfn = sketch_srht_grid_kernel<T, KERNEL, PD, ND, NQ, G>;
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kfn, 256, 0);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) per_cu = 1;
+  int64_t blocks = (n + 3) / 4;
+  const int64_t cap = (int64_t)num_cu * per_cu;
+  if (blocks > cap) blocks = cap;
+  hipLaunchKernelGGL(kfn, dim3((unsigned)blocks), dim3(256), 0, st, pts, cols, n, d, gp, (T)nu_c, Y);
+  return hipGetLastError();
+}
+
+template <typename T, int KERNEL, int PD, int ND, int G>
+static hipError_t launch_srht_grid_nq(hipStream_t st, const T* pts, const int32_t* cols, int64_t n, int d,
+                                      const GridPass<T>& gp, double nc, T* Y, int num_cu) {
+  const int nq = (d + 63) / 64;
+  if (nq <= 1) return launch_srht_grid_impl<T, KERNEL, PD, ND, 1, G>(st, pts, cols, n, d, gp, nc, Y, num_cu);
+  if (nq <= 2) return launch_srht_grid_impl<T, KERNEL, PD, ND, 2, G>(st, pts, cols, n, d, gp, nc, Y, num_cu);
+  if (nq <= 4) return launch_srht_grid_impl<T, KERNEL, PD, ND, 4, G>(st, pts, cols, n, d, gp, nc, Y, num_cu);
+  if (nq <= 8) return launch_srht_grid_impl<T, KERNEL, PD, ND, 8, G>(st, pts, cols, n, d, gp, nc, Y, num_cu);
+  return launch_srht_grid_impl<T, KERNEL, PD, ND, 16, G>(st, pts, cols, n, d, gp, nc, Y, num_cu);
+}
+
+template <typename T, int KERNEL, int G>
+static hipError_t launch_srht_grid_dim(hipStream_t st, int D, const T* pts, const int32_t* cols, int64_t n, int d,
+                                       const GridPass<T>& gp, double nc, T* Y, int num_cu) {
+  switch (D) {
+    case 1: return launch_srht_grid_nq<T, KERNEL, 4, 1, G>(st, pts, cols, n, d, gp, nc, Y, num_cu);
+    case 2: return launch_srht_grid_nq<T, KERNEL, 4, 2, G>(st, pts, cols, n, d, gp, nc, Y, num_cu);
+    case 3: return launch_srht_grid_nq<T, KERNEL, 4, 3, G>(st, pts, cols, n, d, gp, nc, Y, num_cu);
+    default:
+      if (D <= 7) return launch_srht_grid_nq<T, KERNEL, 8, 7, G>(st, pts, cols, n, d, gp, nc, Y, num_cu);
+      return launch_srht_grid_nq<T, KERNEL, 16, 15, G>(st, pts, cols, n, d, gp, nc, Y, num_cu);
+  }
+}
+
+template <typename T>
+hipError_t launch_sketch_srht_grid(hipStream_t st, int kernel, int D, const T* pts, const int32_t* cols, int64_t n,
+                                   int d, int ntheta, const double* dist_scale, const double* scale_out, double nu_c,
+                                   T* Y, int num_cu) {
+  for (int g0 = 0; g0 < ntheta; g0 += kGridPass) {
+    const int gn = ntheta - g0 < kGridPass ? ntheta - g0 : kGridPass;
+    GridPass<T> gp{};
+    for (int g = 0; g < kGridPass; ++g) {
+      const int gg = g0 + (g < gn ? g : 0);
+      gp.a[g] = (T)dist_scale[gg];
+      gp.so[g] = (T)scale_out[gg];
+      gp.yoff[g] = (int64_t)gg * n * d;
+    }
+    hipError_t e;
+    if (gn == kGridPass) {
+      e = kernel == LR_KERNEL_SE
+              ? launch_srht_grid_dim<T, LR_KERNEL_SE, kGridPass>(st, D, pts, cols, n, d, gp, nu_c, Y, num_cu)
+              : launch_srht_grid_dim<T, LR_KERNEL_MATERN32, kGridPass>(st, D, pts, cols, n, d, gp, nu_c, Y, num_cu);
+    } else {
+      e = kernel == LR_KERNEL_SE
+              ? launch_srht_grid_dim<T, LR_KERNEL_SE, 1>(st, D, pts, cols, n, d, gp, nu_c, Y, num_cu)
+              : launch_srht_grid_dim<T, LR_KERNEL_MATERN32, 1>(st, D, pts, cols, n, d, gp, nu_c, Y, num_cu);
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+template hipError_t launch_sketch_srht_grid<float>(hipStream_t, int, int, const float*, const int32_t*, int64_t, int,
+                                                   int, const double*, const double*, double, float*, int);
+template hipError_t launch_sketch_srht_grid<double>(hipStream_t, int, int, const double*, const int32_t*, int64_t,
+                                                    int, int, const double*, const double*, double, double*, int);
 
 template <typename T, int KERNEL, int PD, int ND, int NQ, int MODE>
 static hipError_t launch_srht_impl(hipStream_t st, const T* pts, const int32_t* cols, int64_t n, int d,

@@ -147,3 +147,25 @@ def test_structured_omega_validation():
     assert so(out=None) == L.LR_ERR_ARG
     assert so(out=ctypes.c_void_p(0x10008)) == L.LR_ERR_ARG  # not 16-byte aligned
     assert so(signs=None) == L.LR_ERR_ARG
+
+
+def test_sketch_grid_validation():
+    lib = L.lib()
+    hs = (L.LrHyper * 3)(_hyper(ell=0.2), _hyper(ell=0.3), _hyper(ell=0.4))
+    mixed = (L.LrHyper * 2)(_hyper(), _hyper(kernel=L.LR_KERNEL_MATERN32))
+    bad = (L.LrHyper * 2)(_hyper(), _hyper(ell=-1.0))
+    om = _srht(1024, 64)
+    ws = ctypes.c_void_p(0x100000)
+    g = lambda hyps=hs, nt=3, n=1024, o=om, prec=L.LR_PREC_F32, nu=0.0, y=FAKE, wsb=1 << 30: lib.lr_sketch_grid(
+        None, n, 2, FAKE, nt, ctypes.cast(hyps, ctypes.c_void_p), ctypes.byref(o), nu, prec, y, ws, wsb)
+    assert g(nt=0) == L.LR_ERR_SHAPE
+    assert g(nt=5000) == L.LR_ERR_SHAPE
+    assert g(hyps=mixed, nt=2) == L.LR_ERR_ARG     # one kernel kind per grid
+    assert g(hyps=bad, nt=2) == L.LR_ERR_ARG
+    assert g(nu=-1.0) == L.LR_ERR_ARG
+    assert g(y=None) == L.LR_ERR_ARG
+    assert g(prec=L.LR_PREC_BF16) == L.LR_ERR_UNSUPPORTED  # bf16 with SRHT
+    assert g(n=1000, o=_srht(1000, 64)) == L.LR_ERR_NOT_POW2
+    assert g(wsb=16) == L.LR_ERR_WORKSPACE
+    assert lib.lr_sketch_grid_workspace_bytes(1024, 2, 64, L.LR_PREC_F32) == \
+        lib.lr_sketch_workspace_bytes(1024, 2, 64, L.LR_PREC_F32)
