@@ -19,11 +19,25 @@ F = Omega^T Q, the ill-conditioned W is never inverted:
     log|K_tilde|  = (n - d) log sigma2 + 2 sum_j log L_jj
     loglik        = -1/2 y^T K_tilde^{-1} y - 1/2 log|K_tilde|   (no -n/2 log 2 pi)
 
+Projection variant (the symmetric form of the object Q Q^T K that Sec. 3.1
+bounds in Thm 5, with the further products Sec. 3.3 expects after the QR):
+
+    B = Q^T K_f Q,  optionally replaced by its positive semidefinite part
+        V max(Lambda, 0) V^T (B = V Lambda V^T; the eig-clip core),
+    K_tilde = sigma2 I + Q B Q^T,  S = B + sigma2 I = L L^T,
+
+with the same apply and log-determinant. B is positive semidefinite in exact
+arithmetic for any orthonormal Q; the clip removes what rounding leaves.
+
 Pins (tests/test_oracle_lowrank.py): the dense definition (sigma2 I + Y W^{-1}
 Y^T - nu P_Y)^{-1} A and slogdet on small n; exact recovery of K^{-1} A when
 K_f has rank <= d; exact recovery when d = n (Omega orthogonal); K_f = 0 gives
 A / sigma2; invariance under Omega -> Omega T for orthogonal T; the Cholesky
-info convention on an indefinite S.
+info convention on an indefinite S. Projection: the dense definition
+(sigma2 I + Q Q^T K_f Q Q^T)^{-1} A; exact recovery when range(Q) holds the
+range of a low-rank K_f; the PSD part against the nearest positive
+semidefinite matrix in the Frobenius norm (its distance is the norm of the
+negative eigenvalues), idempotence, and a PSD input left unchanged.
 """
 from __future__ import annotations
 
@@ -121,3 +135,36 @@ def solve_dense(y, omega_dense, sigma2, a, nu=0.0):
     x = np.linalg.solve(kt, np.asarray(a, dtype=np.float64))
     sign, ld = np.linalg.slogdet(kt)
     return x, ld, sign
+
+
+# ---------------------------------------------------------------- projection variant
+
+def psd_part(b: np.ndarray) -> np.ndarray:
+    """V max(Lambda, 0) V^T for symmetric b = V Lambda V^T (eigh)."""
+    b = 0.5 * (np.asarray(b, dtype=np.float64) + np.asarray(b, dtype=np.float64).T)
+    lam, v = np.linalg.eigh(b)
+    return (v * np.maximum(lam, 0.0)) @ v.T
+
+
+def projection_core(q: np.ndarray, kq: np.ndarray, sigma2: float, clip: bool = True):
+    """B = sym(Q^T (K_f Q)) from the second pass kq = K_f Q, optionally clipped
+    to its PSD part; S = B + sigma2 I = L L^T. Returns dict(B, L, info)."""
+    q = np.asarray(q, dtype=np.float64)
+    b = q.T @ np.asarray(kq, dtype=np.float64)
+    b = 0.5 * (b + b.T)
+    if clip:
+        b = psd_part(b)
+    lo, info = cholesky_info(b + sigma2 * np.eye(b.shape[0]))
+    return {"B": b, "L": lo, "info": info}
+
+
+def projection_solve(q, kq, sigma2, a, clip=True):
+    """The projection variant's K_tilde^{-1} A and log|K_tilde| (dict with X,
+    logdet, B, L, info)."""
+    c = projection_core(q, kq, sigma2, clip)
+    if c["info"] != 0:
+        c["X"], c["logdet"] = None, np.nan
+        return c
+    c["X"] = apply(q, c["L"], a, sigma2)
+    c["logdet"] = logdet(c["L"], np.asarray(q).shape[0], sigma2)
+    return c

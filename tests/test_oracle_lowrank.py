@@ -139,3 +139,52 @@ def test_exact_dense_reference_c1_is_reproducible():
     err = np.linalg.norm(fwd["X"] - xe) / np.linalg.norm(xe)
     assert abs(err - gold["c1_method_x_relerr"]) <= 1e-6 * err
     assert 0.0 < err < 1.0
+
+
+def test_psd_part_is_nearest_psd_and_idempotent():
+    rng = np.random.default_rng(3)
+    v = ortho_group.rvs(12, random_state=5)
+    lam = np.array([5.0, 3.0, 2.0, 1.0, 0.5, 0.1, 0.0, -1e-3, -0.2, -1.0, -2.0, -4.0])
+    b = (v * lam) @ v.T
+    bp = lowrank.psd_part(b)
+    np.testing.assert_allclose(bp, bp.T, rtol=0, atol=1e-14)
+    assert np.linalg.eigvalsh(bp).min() >= -1e-13
+    # distance to the PSD cone in the Frobenius norm = norm of the negative part
+    np.testing.assert_allclose(np.linalg.norm(b - bp), np.linalg.norm(lam[lam < 0]), rtol=1e-12)
+    # any other PSD matrix (here random ones) is no closer
+    for _ in range(5):
+        g = rng.standard_normal((12, 12))
+        assert np.linalg.norm(b - g @ g.T) >= np.linalg.norm(b - bp)
+    np.testing.assert_allclose(lowrank.psd_part(bp), bp, rtol=0, atol=1e-13)
+    p = (v * np.abs(lam)) @ v.T
+    np.testing.assert_allclose(lowrank.psd_part(p), p, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("clip", [False, True])
+def test_projection_matches_dense_definition(clip):
+    w = W.small(W.WORKLOADS["C1"], 256, d=24, leaf_rows=64)
+    x = W.points(w).astype(np.float64)
+    a = W.rhs(w, m=3)
+    om = _srht(w)
+    y = sketch.sketch(W.points(w), "se", 0.25, 1.1, om)
+    q, r = qr.tsqr(y, w.leaf_rows)
+    kf = kernels.kernel_matrix("se", x, x, 0.25, 1.1)
+    kq = kf @ q
+    sigma2 = 1e-2
+    out = lowrank.projection_solve(q, kq, sigma2, a, clip=clip)
+    kt = sigma2 * np.eye(w.n) + q @ (q.T @ kf @ q) @ q.T
+    np.testing.assert_allclose(out["X"], np.linalg.solve(kt, a), rtol=1e-9, atol=1e-9 * np.abs(a).max() / sigma2)
+    sign, ld = np.linalg.slogdet(kt)
+    assert sign > 0 and abs(out["logdet"] - ld) <= 1e-10 * abs(ld)
+
+
+def test_projection_exact_when_basis_holds_the_signal():
+    # K_f of rank 8 and a basis whose first 8 columns span its range: K~ = K
+    rng = np.random.default_rng(11)
+    n, d = 200, 20
+    b = rng.standard_normal((n, 8))
+    kf = b @ b.T
+    q, _ = np.linalg.qr(np.hstack([b, rng.standard_normal((n, d - 8))]))
+    a = rng.standard_normal((n, 2))
+    out = lowrank.projection_solve(q, kf @ q, 0.05, a)
+    np.testing.assert_allclose(out["X"], np.linalg.solve(kf + 0.05 * np.eye(n), a), rtol=1e-9, atol=1e-9)
