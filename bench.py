@@ -284,6 +284,22 @@ def loglik_timing(torch, api, W, dev) -> dict:
                 row["grad_err_vs_exact"] = [g[i] - exact[k] for i, k in enumerate(
                     ("c4_grad_logell_exact", "c4_grad_logs_exact", "c4_grad_logsigma2_exact"))]
         out[key] = row
+    # the projection variant in FP32 with no shift (its core stays positive definite)
+    y = torch.from_numpy(yv).to(dev, torch.float32).reshape(-1, 1)
+    state = {}
+
+    def fwd_proj():
+        Y, _ = api.sketch(x, hyp, om, "f32")
+        Q, _ = api.tsqr(Y, w.leaf_rows, "f32")
+        r = api.projection_solve(x, hyp, Q, "f32", w.sigma2, y, clip=True)
+        state["ll"] = api.loglik(y, r.X, r.logdet, r.info, "f32")
+        state["info"] = r.info
+
+    row = {"nu": 0.0, "forward_loglik_ms": _event_ms(fwd_proj, 3, torch, stream),
+           "info": int(state["info"].item()), "loglik": float(state["ll"].item())}
+    if exact is not None:
+        row["loglik_err_vs_exact"] = row["loglik"] - exact["c4_loglik_exact"]
+    out["f32_projection"] = row
     return out
 
 

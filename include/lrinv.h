@@ -216,6 +216,42 @@ lr_status lr_lowrank_solve(void *stream, int64_t n, int32_t d, int32_t m, const 
                            const void *A, void *X, double *C, double *L, double *Flu,
                            int32_t *piv, double *logdet, int32_t *info, void *ws, size_t ws_bytes);
 
+/* ---------------------------------------------------------------- projection variant
+ * The symmetric projection K~_f = Q (Q^T K_f Q) Q^T of the signal covariance
+ * onto the sketch's basis (the object QQ^T K that Sec. 3.1 bounds, Thm 5,
+ * with the further products Sec. 3.3 expects after the QR), with the nugget
+ * added back by Woodbury as in lr_lowrank_solve:
+ *   B = Q^T K_f Q   a second pass of K_f, Q in place of Omega, tiles never
+ *                   stored (float64 for F64, float32 otherwise), the n-length
+ *                   sums exact in float64, then exactly symmetric;
+ *   clip = 1        B <- its positive semidefinite part V max(Lambda, 0) V^T
+ *                   (the eig-clip core; rounding can leave B slightly
+ *                   indefinite), by a Newton-Schulz sign iteration on float64
+ *                   matrix cores;
+ *   S = B + sigma2 I = L L^T, log|K~| = (n - d) log sigma2 + log|S|,
+ *   X = sigma2^{-1} (A - Q Z) + Q S^{-1} Z,  Z = Q^T A  (when m > 0).
+ * No Omega and no R enter, and no shift: B is positive semidefinite in exact
+ * arithmetic for any sketch.
+ *   X       device float32 n x D points; hyp as lr_sketch.
+ *   Q       device real n x d, orthonormal columns (lr_tsqr's output).
+ *   B, L    device float64 d x d outputs (the core used, its Cholesky factor).
+ *   logdet, info  device outputs as lr_lowrank_solve (info > 0: S not PD).
+ *   A, Xout device real n x m (m <= 64; m = 0 computes the factors only).
+ * Workspace: lr_projection_solve_workspace_bytes (points, Q^T, K_f Q, d x d
+ * blocks). Forward only: no adjoint for this variant. */
+size_t lr_projection_solve_workspace_bytes(int64_t n, int32_t D, int32_t d, int32_t m, int32_t prec);
+lr_status lr_projection_solve(void *stream, int64_t n, int32_t D, int32_t d, const float *X, const lr_hyper *hyp,
+                              int32_t prec, const void *Q, double sigma2, int32_t clip, int32_t m, const void *A,
+                              void *Xout, double *B, double *L, double *logdet, int32_t *info, void *ws,
+                              size_t ws_bytes);
+
+/* The positive semidefinite part of a symmetric float64 d x d matrix B
+ * (device, row-major; d <= 1024): Bplus = V max(Lambda, 0) V^T for B = V Lambda
+ * V^T, the eig-clip of the projection core. B is read only (Bplus must not
+ * alias it). Workspace: lr_psd_part_workspace_bytes(d) (3 d^2 doubles). */
+size_t lr_psd_part_workspace_bytes(int32_t d);
+lr_status lr_psd_part(void *stream, int32_t d, const double *B, double *Bplus, void *ws, size_t ws_bytes);
+
 /* ---------------------------------------------------------------- log-likelihood
  * out[0] = -1/2 y^T alpha - 1/2 logdet[0] (the approximate Gaussian
  * log-likelihood without the -n/2 log(2 pi) constant; Sec. 1 names Gaussian
@@ -266,7 +302,7 @@ const char *lr_status_string(int32_t status);
 
 /* ABI version: (major << 16) | minor. 2.0: lr_backward takes the forward's
  * right-hand side A instead of its solution, and R and the shift nu.
- * 2.1: lr_structured_omega, lr_sketch_grid. */
+ * 2.1: lr_structured_omega, lr_sketch_grid, lr_projection_solve, lr_psd_part. */
 int32_t lr_version(void);
 
 #ifdef __cplusplus

@@ -59,6 +59,11 @@ _SIGS = {
     "lr_lowrank_solve": (c_i32, [c_vp, c_i64, c_i32, c_i32, ctypes.POINTER(LrOmega), c_i32, c_vp, c_vp, c_dbl, c_dbl,
                                  c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz]),
     "lr_loglik": (c_i32, [c_vp, c_i64, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "lr_projection_solve_workspace_bytes": (c_sz, [c_i64, c_i32, c_i32, c_i32, c_i32]),
+    "lr_projection_solve": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_vp, ctypes.POINTER(LrHyper), c_i32, c_vp, c_dbl,
+                                    c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz]),
+    "lr_psd_part_workspace_bytes": (c_sz, [c_i32]),
+    "lr_psd_part": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_sz]),
     "lr_backward_workspace_bytes": (c_sz, [c_i64, c_i32, c_i32, c_i32, c_i32]),
     "lr_backward": (c_i32, [c_vp, c_i64, c_i32, c_vp, ctypes.POINTER(LrHyper), ctypes.POINTER(LrOmega), c_i32, c_vp,
                             c_vp, c_vp, c_vp, c_vp, c_vp, c_dbl, c_dbl, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp,

@@ -213,6 +213,54 @@ def lowrank_solve(Q: torch.Tensor, R: torch.Tensor, omega: Omega, prec: str, sig
     return out
 
 
+@dataclasses.dataclass
+class ProjectionOut:
+    X: torch.Tensor | None
+    B: torch.Tensor
+    L: torch.Tensor
+    logdet: torch.Tensor
+    info: torch.Tensor
+
+
+def projection_solve(X: torch.Tensor, hyper: Hyper, Q: torch.Tensor, prec: str, sigma2: float,
+                     A: torch.Tensor | None, clip: bool = True) -> ProjectionOut:
+    """The projection variant K~ = sigma2 I + Q (Q^T K_f Q) Q^T (B clipped to its
+    PSD part with ``clip``) applied to A, through lr_projection_solve."""
+    _check_real(Q, prec, "Q")
+    if X.dtype != torch.float32 or not X.is_contiguous():
+        raise ValueError("points must be contiguous float32")
+    n, d = Q.shape
+    D = X.shape[1]
+    m = 0 if A is None else int(A.shape[1])
+    dev = Q.device
+    if A is not None:
+        _check_real(A, prec, "A")
+    out = torch.empty((n, m), dtype=Q.dtype, device=dev) if m > 0 else None
+    B = torch.empty((d, d), dtype=torch.float64, device=dev)
+    Lf = torch.empty((d, d), dtype=torch.float64, device=dev)
+    logdet = torch.empty(1, dtype=torch.float64, device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    lib = L.lib()
+    ws = _Workspace(lib.lr_projection_solve_workspace_bytes(n, D, d, m, L.PRECS[prec]), dev)
+    h = hyper.struct()
+    L.check(lib.lr_projection_solve(_stream(dev), n, D, d, _p(X), ctypes.byref(h), L.PRECS[prec], _p(Q),
+                                    float(sigma2), 1 if clip else 0, m, _p(A), _p(out), _p(B), _p(Lf), _p(logdet),
+                                    _p(info), ws.ptr, ws.nbytes), "lr_projection_solve")
+    return ProjectionOut(out, B, Lf, logdet, info)
+
+
+def psd_part(B: torch.Tensor) -> torch.Tensor:
+    """V max(Lambda, 0) V^T of a symmetric float64 d x d device matrix (lr_psd_part)."""
+    if B.dtype != torch.float64 or not B.is_contiguous() or B.dim() != 2 or B.shape[0] != B.shape[1]:
+        raise ValueError("B must be a contiguous square float64 tensor")
+    d = int(B.shape[0])
+    out = torch.empty_like(B)
+    lib = L.lib()
+    ws = _Workspace(lib.lr_psd_part_workspace_bytes(d), B.device)
+    L.check(lib.lr_psd_part(_stream(B.device), d, _p(B), _p(out), ws.ptr, ws.nbytes), "lr_psd_part")
+    return out
+
+
 def loglik(y: torch.Tensor, alpha: torch.Tensor, logdet: torch.Tensor, info: torch.Tensor | None,
            prec: str) -> torch.Tensor:
     out = torch.empty(1, dtype=torch.float64, device=y.device)

@@ -320,6 +320,80 @@ TnOperand f64_operand(const double* p, int64_t ld) {
   return op;
 }
 
+// ---------------------------------------------------------------- projection variant
+
+// the float64 second pass for F64, float32 for the float and bf16 paths (Q is float)
+int32_t projection_pass_prec(int32_t prec) { return prec == LR_PREC_F64 ? LR_PREC_F64 : LR_PREC_F32; }
+// Newton-Schulz steps of the PSD part: an eigenvalue of B / ||B||_F down to
+// ~1e-13 reaches its sign (x1.5 per step while small, then quadratically)
+constexpr int kPsdSteps = 96;
+
+struct ProjWs {
+  size_t off_pts, off_qt, off_y2, off_b, off_psd, off_solve, total;
+  SolveWs solve;
+  int64_t ld;
+};
+
+ProjWs proj_layout(int64_t n, int32_t D, int32_t d, int32_t m, int32_t prec) {
+  ProjWs w;
+  const int32_t p2 = projection_pass_prec(prec);
+  const size_t es = real_size(p2);
+  w.ld = (n + 63) / 64 * 64;
+  size_t off = 0;
+  w.off_pts = off;
+  off = al(off + sketch_pts_bytes(n, D, p2));
+  w.off_qt = off;
+  off = al(off + (size_t)d * w.ld * es);
+  w.off_y2 = off;
+  off = al(off + (size_t)n * d * es);
+  w.off_b = off;
+  off = al(off + (size_t)d * d * 8);
+  w.off_psd = off;
+  off = al(off + (size_t)3 * d * d * 8);
+  w.off_solve = off;
+  w.solve = solve_layout(n, d, m);
+  w.total = off + w.solve.total;
+  return w;
+}
+
+lr_status projection_impl(hipStream_t st, int64_t n, int32_t D, int32_t d, const float* X, const lr_hyper* hyp,
+                          int32_t prec, const void* Q, double sigma2, int32_t clip, int32_t m, const void* A,
+                          void* Xout, double* B, double* L, double* logdet, int32_t* info, void* ws) {
+  const ProjWs w = proj_layout(n, D, d, m, prec);
+  const int32_t p2 = projection_pass_prec(prec);
+  const bool f64 = p2 == LR_PREC_F64;
+  char* base = static_cast<char*>(ws);
+  void* pts = base + w.off_pts;
+  void* qt = base + w.off_qt;
+  void* y2 = base + w.off_y2;
+  double* b0 = reinterpret_cast<double*>(base + w.off_b);
+  double* psd = reinterpret_cast<double*>(base + w.off_psd);
+  char* sb = base + w.off_solve;
+  double* Z = reinterpret_cast<double*>(sb + w.solve.off_z);
+  double* W = reinterpret_cast<double*>(sb + w.solve.off_w);
+  double* Wm = reinterpret_cast<double*>(sb + w.solve.off_wm);
+  void* tn = sb + w.solve.off_tn;
+  const int PD = point_stride(D);
+  const double scale = coord_scale(hyp->kernel, hyp->ell);
+  if (f64)
+    LR_HIP(launch_prep_points<double>(st, X, n, D, PD, scale, nullptr, static_cast<double*>(pts)));
+  else
+    LR_HIP(launch_prep_points<float>(st, X, n, D, PD, scale, nullptr, static_cast<float*>(pts)));
+  // second pass Y2 = K_f Q, with Q^T in the transposed dense-Omega layout
+  LR_HIP(launch_transpose(st, n, d, Q, w.ld, qt, f64));
+  LR_HIP(launch_sketch_dense(st, p2, hyp->kernel, D, pts, qt, w.ld, n, d, hyp->s * hyp->s, 0.0, y2, false, nullptr,
+                             num_cu_current()));
+  // B = Q^T K_f Q, summed exactly in float64, then exactly symmetric
+  LR_HIP(launch_gemm_tn(st, n, d, d, real_operand(Q, d, p2), real_operand(y2, d, p2), 1.0, b0, tn, true));
+  LR_HIP(launch_symmetrize(st, d, b0));
+  if (clip)
+    LR_HIP(launch_psd_part(st, d, b0, B, psd, kPsdSteps));
+  else
+    LR_HIP(hipMemcpyAsync(B, b0, (size_t)d * d * sizeof(double), hipMemcpyDeviceToDevice, st));
+  LR_HIP(launch_chol_core(st, n, d, B, sigma2, L, logdet, info));
+  return woodbury_apply(st, n, d, m, p2, Q, L, sigma2, info, A, Xout, Z, W, Wm, tn);
+}
+
 }  // namespace
 
 extern "C" {
@@ -522,6 +596,45 @@ lr_status lr_lowrank_solve(void* stream, int64_t n, int32_t d, int32_t m, const 
   LR_HIP(launch_gemm_tn(st, n, d, d, om, real_operand(Q, d, prec), oscale, F, tn, f64));
   LR_HIP(launch_core(st, n, d, F, R, sigma2, nu, Flu, piv, C, L, logdet, info));
   return woodbury_apply(st, n, d, m, prec, Q, L, sigma2, info, A, X, Z, W, Wm, tn);
+}
+
+size_t lr_projection_solve_workspace_bytes(int64_t n, int32_t D, int32_t d, int32_t m, int32_t prec) {
+  if (check_sizes(n, d) != LR_OK || D < 1 || D > 15 || m < 0 || m > 64 || !valid_prec(prec)) return 0;
+  return proj_layout(n, D, d, m, prec).total;
+}
+
+lr_status lr_projection_solve(void* stream, int64_t n, int32_t D, int32_t d, const float* X, const lr_hyper* hyp,
+                              int32_t prec, const void* Q, double sigma2, int32_t clip, int32_t m, const void* A,
+                              void* Xout, double* B, double* L, double* logdet, int32_t* info, void* ws,
+                              size_t ws_bytes) {
+  if (!valid_prec(prec)) return LR_ERR_ARG;
+  if (D < 1 || D > 15) return LR_ERR_SHAPE;
+  lr_status s = check_sizes(n, d);
+  if (s != LR_OK) return s;
+  if (m < 0 || m > 64) return LR_ERR_SHAPE;
+  if (clip != 0 && clip != 1) return LR_ERR_ARG;
+  if ((s = check_hyper(hyp)) != LR_OK) return s;
+  if (!is_fin(sigma2) || !(sigma2 > 0.0)) return LR_ERR_ARG;
+  if (X == nullptr || Q == nullptr || B == nullptr || L == nullptr || logdet == nullptr || info == nullptr)
+    return LR_ERR_ARG;
+  if (m > 0 && (A == nullptr || Xout == nullptr || A == Xout)) return LR_ERR_ARG;
+  if ((s = check_ws(proj_layout(n, D, d, m, prec).total, ws, ws_bytes)) != LR_OK) return s;
+  return projection_impl(static_cast<hipStream_t>(stream), n, D, d, X, hyp, prec, Q, sigma2, clip, m, A, Xout, B, L,
+                         logdet, info, ws);
+}
+
+size_t lr_psd_part_workspace_bytes(int32_t d) {
+  if (d < 1 || d > 1024) return 0;
+  return al((size_t)3 * d * d * sizeof(double));
+}
+
+lr_status lr_psd_part(void* stream, int32_t d, const double* B, double* Bplus, void* ws, size_t ws_bytes) {
+  if (d < 1 || d > 1024) return LR_ERR_SHAPE;
+  if (B == nullptr || Bplus == nullptr || B == Bplus) return LR_ERR_ARG;
+  lr_status s = check_ws(lr_psd_part_workspace_bytes(d), ws, ws_bytes);
+  if (s != LR_OK) return s;
+  LR_HIP(launch_psd_part(static_cast<hipStream_t>(stream), d, B, Bplus, static_cast<double*>(ws), kPsdSteps));
+  return LR_OK;
 }
 
 lr_status lr_loglik(void* stream, int64_t n, int32_t prec, const void* y, const void* alpha, const double* logdet,

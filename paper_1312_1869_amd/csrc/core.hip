@@ -339,7 +339,7 @@ __global__ __launch_bounds__(256) void chol_update_kernel(int d, double* L, int 
   }
 }
 
-__global__ void shift_lower_kernel(int d, double sigma2, double nu, double* C, double* L,
+__global__ void shift_lower_kernel(int d, double sigma2, double nu, const double* C, double* L,
                                    const int32_t* __restrict__ info) {
   if (*info != 0) return;
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -379,6 +379,9 @@ __global__ void init_info_kernel(const double* __restrict__ F, double* Flu, int6
   if (e == 0) *info = 0;
 }
 
+static hipError_t chol_logdet(hipStream_t st, int64_t n, int d, double sigma2, double* L, double* logdet,
+                              int32_t* info);
+
 hipError_t launch_core(hipStream_t st, int64_t n, int d, const double* F, const double* R, double sigma2, double nu,
                        double* Flu, int32_t* piv, double* C, double* L, double* logdet, int32_t* info) {
   const int64_t dd = (int64_t)d * d;
@@ -410,6 +413,27 @@ hipError_t launch_core(hipStream_t st, int64_t n, int d, const double* F, const 
   if ((e = launch_trsm_cols(st, false, d, d, Flu, piv, 1, R, C, d, info)) != hipSuccess) return e;
   hipLaunchKernelGGL(shift_lower_kernel, dim3(ddb), dim3(256), 0, st, d, sigma2, nu, C, L, info);
   hipLaunchKernelGGL(sym_kernel, dim3(ddb), dim3(256), 0, st, d, C, info);
+  return chol_logdet(st, n, d, sigma2, L, logdet, info);
+}
+
+__global__ void zero_info_kernel(int32_t* info) { *info = 0; }
+
+hipError_t launch_chol_core(hipStream_t st, int64_t n, int d, const double* B, double sigma2, double* L,
+                            double* logdet, int32_t* info) {
+  const int64_t dd = (int64_t)d * d;
+  const unsigned ddb = (unsigned)((dd + 255) / 256);
+  hipLaunchKernelGGL(zero_info_kernel, dim3(1), dim3(1), 0, st, info);
+  hipLaunchKernelGGL(shift_lower_kernel, dim3(ddb), dim3(256), 0, st, d, sigma2, 0.0, B, L, info);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return chol_logdet(st, n, d, sigma2, L, logdet, info);
+}
+
+// Cholesky of the lower part of S held in L (blocked, in place) and the
+// log-determinant (n - d) log sigma2 + 2 sum log L_kk; a non-positive pivot
+// sets *info and every later kernel does nothing.
+static hipError_t chol_logdet(hipStream_t st, int64_t n, int d, double sigma2, double* L, double* logdet,
+                              int32_t* info) {
   for (int k0 = 0; k0 < d; k0 += kPanel) {
     // the smallest workgroup with a thread for each row below the diagonal block
     const int below = d - min(k0 + kPanel, d);

@@ -19,6 +19,14 @@
 //    identity (an inverse). A third mode applies only an upper triangle
 //    (R^{-1} B for the TSQR factor).
 //  * lu_apply: F B from the getrf factors of F.
+//  * psd_part: the positive semidefinite part V max(Lambda, 0) V^T of a
+//    symmetric matrix (the eig-clip core), without an eigendecomposition:
+//    B+ = (B + B sign(B)) / 2 with sign(B) from the Newton-Schulz iteration
+//    X <- X (3I - X^2) / 2 started at B / ||B||_F. Every eigenvalue of X stays
+//    in [-1, 1] and moves towards its sign, by a factor 1.5 per step while
+//    small and quadratically near +-1; an eigenvalue still unresolved when
+//    the steps end is one below ~1e-13 ||B||, whose clipping cannot matter at
+//    float64 precision. Two gemm_dd per step, all on float64 matrix cores.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -323,6 +331,71 @@ hipError_t launch_lu_apply(hipStream_t st, int d, int nrhs, const double* Flu, c
   if (d < 1 || d > kTrMaxD) return hipErrorInvalidValue;
   hipLaunchKernelGGL(lu_apply_kernel, dim3((unsigned)nrhs), dim3(256), 0, st, d, nrhs, Flu, piv, B, out, ld);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ psd_part
+
+// X0 = B / ||B||_F (one workgroup: the norm, then the scaled copy).
+__global__ __launch_bounds__(1024) void frob_scale_kernel(int d, const double* __restrict__ B, double* __restrict__ X) {
+  __shared__ double red[16];
+  const int64_t dd = (int64_t)d * d;
+  double part = 0.0;
+  for (int64_t e = threadIdx.x; e < dd; e += blockDim.x) part += B[e] * B[e];
+  for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+  __syncthreads();
+  double tot = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += red[w];
+  const double inv = tot > 0.0 ? 1.0 / sqrt(tot) : 0.0;
+  for (int64_t e = threadIdx.x; e < dd; e += blockDim.x) X[e] = B[e] * inv;
+}
+
+// out = c I (d x d)
+__global__ void scaled_identity_kernel(int d, double c, double* __restrict__ out) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < (int64_t)d * d) out[e] = (e / d == e % d) ? c : 0.0;
+}
+
+// M <- (M + M^T) / 2 in place (one thread per entry pair i < j).
+__global__ void symmetrize_kernel(int d, double* __restrict__ M) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)d * d) return;
+  const int i = (int)(e / d), j = (int)(e % d);
+  if (i < j) {
+    const double v = 0.5 * (M[e] + M[(int64_t)j * d + i]);
+    M[e] = v;
+    M[(int64_t)j * d + i] = v;
+  }
+}
+
+hipError_t launch_symmetrize(hipStream_t st, int d, double* M) {
+  const int64_t dd = (int64_t)d * d;
+  hipLaunchKernelGGL(symmetrize_kernel, dim3((unsigned)((dd + 255) / 256)), dim3(256), 0, st, d, M);
+  return hipGetLastError();
+}
+
+hipError_t launch_psd_part(hipStream_t st, int d, const double* B, double* Bplus, double* ws, int steps) {
+  const int64_t dd = (int64_t)d * d;
+  const unsigned ddb = (unsigned)((dd + 255) / 256);
+  double* X = ws;
+  double* Xn = ws + dd;
+  double* T = ws + 2 * dd;
+  hipLaunchKernelGGL(frob_scale_kernel, dim3(1), dim3(1024), 0, st, d, B, X);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  for (int k = 0; k < steps; ++k) {
+    hipLaunchKernelGGL(scaled_identity_kernel, dim3(ddb), dim3(256), 0, st, d, 3.0, T);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_gemm_dd(st, d, d, d, -1.0, X, d, false, X, d, false, 1.0, T, d)) != hipSuccess) return e;
+    if ((e = launch_gemm_dd(st, d, d, d, 0.5, X, d, false, T, d, false, 0.0, Xn, d)) != hipSuccess) return e;
+    double* t = X;
+    X = Xn;
+    Xn = t;
+  }
+  // B+ = B / 2 + B X / 2, then exact symmetry
+  if ((e = hipMemcpyAsync(Bplus, B, dd * sizeof(double), hipMemcpyDeviceToDevice, st)) != hipSuccess) return e;
+  if ((e = launch_gemm_dd(st, d, d, d, 0.5, B, d, false, X, d, false, 0.5, Bplus, d)) != hipSuccess) return e;
+  return launch_symmetrize(st, d, Bplus);
 }
 
 }  // namespace lr

@@ -67,6 +67,8 @@ hipError_t launch_narrow(hipStream_t st, int64_t count, const double* in, float*
 hipError_t launch_wmix(hipStream_t st, int64_t count, const double* W, const double* Z, double sigma2,
                        const int32_t* info, double* out);
 hipError_t launch_fill(hipStream_t st, double* out, int64_t count, double v);
+// out (d x ld) = Q^T for a row-major n x d Q (float or double), zero columns past n.
+hipError_t launch_transpose(hipStream_t st, int64_t n, int d, const void* Q, int64_t ld, void* out, bool f64);
 
 // core.hip
 hipError_t launch_core(hipStream_t st, int64_t n, int d, const double* F, const double* R, double sigma2, double nu,
@@ -75,6 +77,10 @@ hipError_t launch_core(hipStream_t st, int64_t n, int d, const double* F, const 
 // when *info != 0.
 hipError_t launch_core_apply(hipStream_t st, int d, int m, const double* L, const double* Z, double sigma2,
                              const int32_t* info, double* Wfull, double* Wmix);
+// S = sym(B) + sigma2 I, its Cholesky factor in L (lower) and the
+// log-determinant; *info = 0 first, the failing pivot on breakdown.
+hipError_t launch_chol_core(hipStream_t st, int64_t n, int d, const double* B, double sigma2, double* L,
+                            double* logdet, int32_t* info);
 hipError_t launch_loglik(hipStream_t st, int64_t n, bool f64, const void* y, const void* alpha, const double* logdet,
                          const int32_t* info, double* out);
 // Scalars of the hyperparameter adjoint (see lr_backward and dense.hip).
@@ -144,5 +150,9 @@ hipError_t launch_trsm_upper(hipStream_t st, int d, int nrhs, const double* U, c
 hipError_t launch_lu_apply(hipStream_t st, int d, int nrhs, const double* Flu, const int32_t* piv, const double* B,
                            double* out, int ld);
 hipError_t launch_identity(hipStream_t st, double* X, int d);
+// The positive semidefinite part of a symmetric d x d matrix (dense.hip);
+// ws holds 3 d^2 doubles.
+hipError_t launch_psd_part(hipStream_t st, int d, const double* B, double* Bplus, double* ws, int steps);
+hipError_t launch_symmetrize(hipStream_t st, int d, double* M);
 
 }  // namespace lr

@@ -339,6 +339,37 @@ __global__ void fill_kernel(double* __restrict__ out, int64_t count, double v) {
   if (idx < count) out[idx] = v;
 }
 
+// out (d x ld, j contiguous) = Q^T for a row-major n x d Q, columns n .. ld-1
+// zeroed: the transposed dense-Omega layout, so Q can stand in for Omega in
+// a second sketch pass. 32 x 32 tiles through LDS keep both sides coalesced.
+template <typename T>
+__global__ void transpose_kernel(int64_t n, int d, const T* __restrict__ Q, int64_t ld, T* __restrict__ out) {
+  __shared__ T tile[32][33];
+  const int64_t j0 = (int64_t)blockIdx.x * 32;
+  const int c0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 8 rows per pass
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t j = j0 + r;
+    const int c = c0 + tx;
+    tile[r][tx] = (j < n && c < d) ? Q[j * d + c] : (T)0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int c = c0 + r;
+    const int64_t j = j0 + tx;
+    if (c < d && j < ld) out[(int64_t)c * ld + j] = tile[tx][r];
+  }
+}
+
+hipError_t launch_transpose(hipStream_t st, int64_t n, int d, const void* Q, int64_t ld, void* out, bool f64) {
+  const dim3 grid((unsigned)((ld + 31) / 32), (unsigned)((d + 31) / 32));
+  if (f64)
+    hipLaunchKernelGGL(transpose_kernel<double>, grid, dim3(256), 0, st, n, d, (const double*)Q, ld, (double*)out);
+  else
+    hipLaunchKernelGGL(transpose_kernel<float>, grid, dim3(256), 0, st, n, d, (const float*)Q, ld, (float*)out);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill(hipStream_t st, double* out, int64_t count, double v) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, out, count, v);

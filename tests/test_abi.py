@@ -169,3 +169,27 @@ def test_sketch_grid_validation():
     assert g(wsb=16) == L.LR_ERR_WORKSPACE
     assert lib.lr_sketch_grid_workspace_bytes(1024, 2, 64, L.LR_PREC_F32) == \
         lib.lr_sketch_workspace_bytes(1024, 2, 64, L.LR_PREC_F32)
+
+
+def test_projection_and_psd_validation():
+    lib = L.lib()
+    hyp = _hyper()
+    ws = ctypes.c_void_p(0x100000)
+    pj = lambda n=4096, d=64, m=2, prec=L.LR_PREC_F32, sigma2=1e-3, clip=1, A=FAKE, X=ctypes.c_void_p(0x20000), \
+        wsb=1 << 40, D=2: lib.lr_projection_solve(None, n, D, d, FAKE, ctypes.byref(hyp), prec, FAKE, sigma2, clip, m,
+                                                  A, X, FAKE, FAKE, FAKE, FAKE, ws, wsb)
+    assert pj(clip=2) == L.LR_ERR_ARG
+    assert pj(sigma2=0.0) == L.LR_ERR_ARG
+    assert pj(prec=5) == L.LR_ERR_ARG
+    assert pj(d=2048) == L.LR_ERR_SHAPE
+    assert pj(d=5000, n=4096) == L.LR_ERR_SHAPE
+    assert pj(m=65) == L.LR_ERR_SHAPE
+    assert pj(D=16) == L.LR_ERR_SHAPE
+    assert pj(A=FAKE, X=FAKE) == L.LR_ERR_ARG
+    assert pj(wsb=64) == L.LR_ERR_WORKSPACE
+    assert lib.lr_projection_solve_workspace_bytes(4096, 2, 64, 2, L.LR_PREC_F32) > 4096 * 64 * 8
+    assert lib.lr_psd_part(None, 0, FAKE, FAKE, ws, 1 << 30) == L.LR_ERR_SHAPE
+    assert lib.lr_psd_part(None, 2000, FAKE, FAKE, ws, 1 << 30) == L.LR_ERR_SHAPE
+    assert lib.lr_psd_part(None, 64, FAKE, FAKE, ws, 1 << 30) == L.LR_ERR_ARG  # Bplus aliases B
+    assert lib.lr_psd_part(None, 64, FAKE, ctypes.c_void_p(0x30000), ws, 8) == L.LR_ERR_WORKSPACE
+    assert lib.lr_psd_part_workspace_bytes(64) >= 3 * 64 * 64 * 8
