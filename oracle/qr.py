@@ -21,10 +21,17 @@ Q_leaf [M_leaf; 0]. Finally the signs are fixed so that diag(R) >= 0 (row j of
 R and column j of Q are negated together when R_jj < 0), which makes R the
 unique triangular factor with non-negative diagonal.
 
+tsqr_grouped runs the other scheme Sec. 3.3 gives, Eq. (5): inside groups of
+consecutive blocks the QR goes in sequence, each step factoring the previous
+R stacked on the next block; the groups' R factors then meet in the binary
+tree (one group of all blocks is the fully sequential scheme; the paper
+expects mixtures of the two to be best).
+
 Pins (tests/test_oracle_qr.py): R against numpy.linalg.qr (sign-normalised);
 Q R = A and Q^T Q = I to round-off; exact zeros below the diagonal of R; the
 tau = 0 case on a zero column; one leaf identical to the plain factorisation;
-R independent of the block size (tree shape).
+R independent of the block size (tree shape); the grouped scheme against
+LAPACK for every group size, and with group = 1 equal to tsqr.
 """
 from __future__ import annotations
 
@@ -140,6 +147,43 @@ def tsqr(y: np.ndarray, leaf_rows: int, normalize_signs: bool = True):
         b[:d] = m
         q[r0:r1] = apply_q(v, tau, b)
 
+    if normalize_signs:
+        neg = np.diag(r_final) < 0.0
+        r_final[neg, :] *= -1.0
+        q[:, neg] *= -1.0
+    return q, r_final
+
+
+def tsqr_grouped(y: np.ndarray, leaf_rows: int, group: int, normalize_signs: bool = True):
+    """Blocked QR with the sequential scheme of Eq. (5) inside groups of
+    ``group`` consecutive row blocks, and the binary tree of Eq. (2)-(4) over
+    the groups' R factors. Inside a group: the QR of the first block, then
+    for every further block K_t the QR of [R_{t-1}; K_t]; the group's rows of Q
+    follow from [Q_prev R_{t-1}; K_t] = [Q_prev Q_t^top; Q_t^bottom] R_t.
+    group = 1 is tsqr itself. Returns (Q n x d, R d x d)."""
+    y = np.asarray(y, dtype=np.float64)
+    n, d = y.shape
+    bounds = leaf_bounds(n, leaf_rows, d)
+    if group < 1 or len(bounds) % group != 0:
+        raise ValueError("the number of row blocks must be a multiple of group")
+    # each group reduced in sequence to (rows of the group, Q_group, R_group)
+    groups = []
+    for g0 in range(0, len(bounds), group):
+        blocks = bounds[g0:g0 + group]
+        v, tau, r = householder_qr(y[blocks[0][0]:blocks[0][1]])
+        m0 = blocks[0][1] - blocks[0][0]
+        qg = apply_q(v, tau, np.vstack([np.eye(d), np.zeros((m0 - d, d))]))
+        for (r0, r1) in blocks[1:]:
+            v, tau, r = householder_qr(np.vstack([r, y[r0:r1]]))
+            qt = apply_q(v, tau, np.vstack([np.eye(d), np.zeros((r1 - r0, d))]))
+            qg = np.vstack([qg @ qt[:d], qt[d:]])
+        groups.append((blocks[0][0], blocks[-1][1], qg, r))
+    # the binary tree over the group R factors (each group a block of rows)
+    rows = np.vstack([g[3] for g in groups])
+    q_top, r_final = tsqr(rows, d, normalize_signs=False)
+    q = np.empty((n, d))
+    for k, (r0, r1, qg, _) in enumerate(groups):
+        q[r0:r1] = qg @ q_top[k * d:(k + 1) * d]
     if normalize_signs:
         neg = np.diag(r_final) < 0.0
         r_final[neg, :] *= -1.0

@@ -70,3 +70,25 @@ def test_leaf_shape_errors():
     with pytest.raises(ValueError):
         qr.leaf_bounds(100, 48, 16)  # last block has 4 < 16 rows
     assert qr.leaf_bounds(100, 42, 16) == [(0, 42), (42, 84), (84, 100)]
+
+
+@pytest.mark.parametrize("group", [1, 2, 4, 8])
+def test_grouped_sequential_scheme_matches_lapack(group):
+    rng = np.random.default_rng(group)
+    n, d, leaf = 8 * 40, 12, 40
+    a = rng.standard_normal((n, d)) @ np.diag(np.logspace(0, -6, d))
+    q, r = qr.tsqr_grouped(a, leaf, group)
+    q_ref, r_ref = np.linalg.qr(a)
+    sg = np.where(np.diag(r_ref) < 0, -1.0, 1.0)
+    np.testing.assert_allclose(r, r_ref * sg[:, None], rtol=0, atol=1e-12 * np.abs(r_ref).max())
+    np.testing.assert_allclose(q, q_ref * sg[None, :], rtol=0, atol=1e-9)
+    np.testing.assert_allclose(q @ r, a, rtol=0, atol=1e-13 * np.abs(a).max())
+    assert np.all(np.tril(r, -1) == 0.0) and np.all(np.diag(r) >= 0)
+    if group == 1:
+        q1, r1 = qr.tsqr(a, leaf)
+        np.testing.assert_allclose(r, r1, rtol=0, atol=1e-14 * np.abs(r1).max())
+
+
+def test_grouped_scheme_needs_whole_groups():
+    with pytest.raises(ValueError):
+        qr.tsqr_grouped(np.ones((300, 4)), 100, 2)
