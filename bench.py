@@ -497,6 +497,16 @@ def main() -> int:
         result["c1_exact"] = c1_error_vs_exact(torch, api, W, dev)
         result["structured_omega"] = structured_rates(torch, api, W, dev)
         result["hyperparameter_grid"] = grid_rates(torch, api, W, dev)
+        # blocked-QR shapes on this workload's sketch: the binary tree with and
+        # without forming Q, and groups of 2 and 4 blocks run in sequence (Eq. 5)
+        Ys, _ = api.sketch(X, hyp, om, prec)
+        shapes = {}
+        for g, want_q in ((1, True), (1, False), (2, True), (4, True)):
+            key = f"group{g}" + ("" if want_q else "_r_only")
+            shapes[key] = _event_ms(lambda: api.tsqr_tree(Ys, w.leaf_rows, rp, group=g, want_q=want_q), 3, torch,
+                                    stream)
+        result["tsqr_shapes_ms"] = shapes
+        del Ys
 
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w, x, om_np, flops["sketch"])

@@ -194,6 +194,23 @@ size_t lr_tsqr_workspace_bytes(int64_t n, int32_t d, int32_t leaf_rows, int32_t 
 lr_status lr_tsqr(void *stream, int64_t n, int32_t d, int32_t leaf_rows, int32_t prec,
                   const void *Y, void *Q, double *R, void *ws, size_t ws_bytes);
 
+/* Tree shapes of the blocked QR and R without Q (Sec. 3.3). With group = 1
+ * this is lr_tsqr's binary tree (Eq. 2-4). With group = g > 1 the leaves are
+ * taken in groups of g consecutive blocks and each group runs the sequential
+ * scheme of Eq. (5): the first block's QR, then the QR of the previous R
+ * stacked on the next block, [R_{t-1}; K_t], in the working precision; the
+ * groups' R factors then meet in the float64 binary tree. group = number of
+ * blocks is the fully sequential scheme, and 1 < group < blocks the hybrids
+ * between the two. Q may be NULL: only R is computed and Q is never formed
+ * (all a caller needing R^{-1} alone requires, Sec. 3.3).
+ *   group > 1 needs n % leaf_rows == 0, (n / leaf_rows) % group == 0 and
+ *   d + leaf_rows <= 8192 (LR_ERR_SHAPE otherwise).
+ * Outputs, precisions and errors otherwise as lr_tsqr; R (diag >= 0) and Q are
+ * those of lr_tsqr up to rounding. Workspace: lr_tsqr_tree_workspace_bytes. */
+size_t lr_tsqr_tree_workspace_bytes(int64_t n, int32_t d, int32_t leaf_rows, int32_t group, int32_t prec);
+lr_status lr_tsqr_tree(void *stream, int64_t n, int32_t d, int32_t leaf_rows, int32_t group, int32_t prec,
+                       const void *Y, void *Q, double *R, void *ws, size_t ws_bytes);
+
 /* ---------------------------------------------------------------- lowrank_solve
  * X = K~^{-1} A and log|K~| from the sketch factors (see the header comment).
  *   Q, R        outputs of lr_tsqr for the same Omega and nu.
@@ -302,7 +319,8 @@ const char *lr_status_string(int32_t status);
 
 /* ABI version: (major << 16) | minor. 2.0: lr_backward takes the forward's
  * right-hand side A instead of its solution, and R and the shift nu.
- * 2.1: lr_structured_omega, lr_sketch_grid, lr_projection_solve, lr_psd_part. */
+ * 2.1: lr_structured_omega, lr_sketch_grid, lr_projection_solve, lr_psd_part,
+ * lr_tsqr_tree. */
 int32_t lr_version(void);
 
 #ifdef __cplusplus

@@ -55,6 +55,8 @@ _SIGS = {
                                c_vp, c_sz]),
     "lr_tsqr_workspace_bytes": (c_sz, [c_i64, c_i32, c_i32, c_i32]),
     "lr_tsqr": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_sz]),
+    "lr_tsqr_tree_workspace_bytes": (c_sz, [c_i64, c_i32, c_i32, c_i32, c_i32]),
+    "lr_tsqr_tree": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_sz]),
     "lr_lowrank_solve_workspace_bytes": (c_sz, [c_i64, c_i32, c_i32, c_i32]),
     "lr_lowrank_solve": (c_i32, [c_vp, c_i64, c_i32, c_i32, ctypes.POINTER(LrOmega), c_i32, c_vp, c_vp, c_dbl, c_dbl,
                                  c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz]),

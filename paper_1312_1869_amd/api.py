@@ -191,6 +191,21 @@ class SolveOut:
     info: torch.Tensor
 
 
+def tsqr_tree(Y: torch.Tensor, leaf_rows: int, prec: str, group: int = 1, want_q: bool = True):
+    """Blocked QR with groups of ``group`` blocks run sequentially (Eq. 5) under
+    the binary tree; ``want_q=False`` returns (None, R) without forming Q."""
+    _check_real(Y, prec, "Y")
+    n, d = Y.shape
+    dev = Y.device
+    Q = torch.empty_like(Y) if want_q else None
+    R = torch.empty((d, d), dtype=torch.float64, device=dev)
+    lib = L.lib()
+    ws = _Workspace(lib.lr_tsqr_tree_workspace_bytes(n, d, int(leaf_rows), int(group), L.PRECS[prec]), dev)
+    L.check(lib.lr_tsqr_tree(_stream(dev), n, d, int(leaf_rows), int(group), L.PRECS[prec], _p(Y), _p(Q), _p(R),
+                             ws.ptr, ws.nbytes), "lr_tsqr_tree")
+    return Q, R
+
+
 def lowrank_solve(Q: torch.Tensor, R: torch.Tensor, omega: Omega, prec: str, sigma2: float,
                   A: torch.Tensor | None, nu: float = 0.0) -> SolveOut:
     _check_real(Q, prec, "Q")

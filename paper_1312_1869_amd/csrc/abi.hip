@@ -561,6 +561,42 @@ lr_status lr_tsqr(void* stream, int64_t n, int32_t d, int32_t leaf_rows, int32_t
   return e == hipSuccess ? LR_OK : LR_ERR_HIP;
 }
 
+size_t lr_tsqr_tree_workspace_bytes(int64_t n, int32_t d, int32_t leaf_rows, int32_t group, int32_t prec) {
+  if (!valid_prec(prec) || check_sizes(n, d) != LR_OK || leaf_rows < d || leaf_rows > 8192 || group < 1) return 0;
+  if (group == 1) return tsqr_workspace(n, d, leaf_rows, prec == LR_PREC_F64);
+  if (n % leaf_rows != 0 || (n / leaf_rows) % group != 0 || d + leaf_rows > 8192) return 0;
+  return tsqr_domino_workspace(n, d, leaf_rows, group, prec == LR_PREC_F64);
+}
+
+lr_status lr_tsqr_tree(void* stream, int64_t n, int32_t d, int32_t leaf_rows, int32_t group, int32_t prec,
+                       const void* Y, void* Q, double* R, void* ws, size_t ws_bytes) {
+  if (!valid_prec(prec)) return LR_ERR_ARG;
+  lr_status s = check_sizes(n, d);
+  if (s != LR_OK) return s;
+  if (leaf_rows < d || leaf_rows > 8192 || group < 1) return LR_ERR_SHAPE;
+  const int64_t nleaf = (n + leaf_rows - 1) / leaf_rows;
+  if (group == 1) {
+    if (n - (nleaf - 1) * leaf_rows < d) return LR_ERR_SHAPE;
+  } else {
+    if (n % leaf_rows != 0 || nleaf % group != 0 || d + leaf_rows > 8192) return LR_ERR_SHAPE;
+  }
+  if (Y == nullptr || R == nullptr) return LR_ERR_ARG;
+  if ((s = check_ws(lr_tsqr_tree_workspace_bytes(n, d, leaf_rows, group, prec), ws, ws_bytes)) != LR_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (prec == LR_PREC_F64) {
+    e = group == 1 ? tsqr_run<double>(st, n, d, leaf_rows, static_cast<const double*>(Y), static_cast<double*>(Q), R,
+                                      ws)
+                   : tsqr_domino_run<double>(st, n, d, leaf_rows, group, static_cast<const double*>(Y),
+                                             static_cast<double*>(Q), R, ws);
+  } else {
+    e = group == 1 ? tsqr_run<float>(st, n, d, leaf_rows, static_cast<const float*>(Y), static_cast<float*>(Q), R, ws)
+                   : tsqr_domino_run<float>(st, n, d, leaf_rows, group, static_cast<const float*>(Y),
+                                            static_cast<float*>(Q), R, ws);
+  }
+  return e == hipSuccess ? LR_OK : LR_ERR_HIP;
+}
+
 size_t lr_lowrank_solve_workspace_bytes(int64_t n, int32_t d, int32_t m, int32_t prec) {
   if (check_sizes(n, d) != LR_OK || m < 0 || m > 64 || !valid_prec(prec)) return 0;
   return solve_layout(n, d, m).total;

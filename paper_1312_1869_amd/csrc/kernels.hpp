@@ -36,6 +36,13 @@ size_t omega_frag_bytes(int64_t n, int d);
 size_t tsqr_workspace(int64_t n, int d, int leaf_rows, bool f64);
 template <typename T>
 hipError_t tsqr_run(hipStream_t st, int64_t n, int d, int leaf_rows, const T* Y, T* Q, double* R, void* ws);
+// Sequential groups of `group` blocks (Eq. 5), then the binary tree over the
+// groups; n a multiple of leaf_rows, the block count a multiple of group,
+// d + leaf_rows <= 8192. Q may be NULL (R only).
+size_t tsqr_domino_workspace(int64_t n, int d, int leaf_rows, int group, bool f64);
+template <typename T>
+hipError_t tsqr_domino_run(hipStream_t st, int64_t n, int d, int leaf_rows, int group, const T* Y, T* Q, double* R,
+                           void* ws);
 
 // linalg.hip
 // Operand of a transposed product sum_r X(r, i) Y(r, j) over rows r.

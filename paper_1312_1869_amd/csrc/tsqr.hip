@@ -1083,14 +1083,111 @@ static hipError_t batched_apply_q(hipStream_t st, const T* V, int64_t vstride, T
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+template <typename T>
+static hipError_t launch_copy(hipStream_t st, const T* src, T* dst, int64_t count) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_kernel<T>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, src, dst, count);
+  return hipGetLastError();
+}
+
+// The binary tree over b R factors (Eq. 2-3) and the push of the d x d blocks
+// back down it (Eq. 4): workspace offsets per level.
+struct TreePlan {
+  std::vector<int> count;  // R factors per level (level 0 = the tree's leaves)
+  std::vector<int> pairs;  // nodes per tree level
+  std::vector<size_t> off_r, off_m, off_node, off_ntau, off_nt, off_ntbig, off_ngram;
+  size_t end;
+};
+
+static TreePlan make_tree_plan(int nleaf, int d, size_t off) {
+  TreePlan p;
+  int c = nleaf;
+  p.count.push_back(c);
+  while (c > 1) {
+    p.pairs.push_back(c / 2);
+    c = (c + 1) / 2;
+    p.count.push_back(c);
+  }
+  const size_t dd = (size_t)d * d * sizeof(double);
+  const size_t blk = (size_t)kOuter * kOuter;
+  for (size_t l = 0; l < p.count.size(); ++l) {
+    p.off_r.push_back(off);
+    off = align256(off + (size_t)p.count[l] * dd);
+    p.off_m.push_back(off);
+    off = align256(off + (size_t)p.count[l] * dd);
+  }
+  for (size_t l = 0; l < p.pairs.size(); ++l) {
+    QrShape ns = qr_shape<double>(2 * d, 2 * d, p.pairs[l], d, true);
+    p.off_node.push_back(off);
+    off = align256(off + (size_t)p.pairs[l] * 2 * dd);
+    p.off_ntau.push_back(off);
+    off = align256(off + (size_t)p.pairs[l] * d * sizeof(double));
+    p.off_nt.push_back(off);
+    off = align256(off + (size_t)p.pairs[l] * ns.npanels * ns.nb * ns.nb * sizeof(double));
+    p.off_ntbig.push_back(off);
+    off = align256(off + (size_t)n_outer(d) * p.pairs[l] * blk * sizeof(double));
+    p.off_ngram.push_back(off);
+    off = align256(off + (size_t)p.pairs[l] * blk * sizeof(double));
+  }
+  p.end = off;
+  return p;
+}
+
+// Reduces the count[0] R factors at off_r[0] to R (diag >= 0) and, with
+// want_q, leaves the d x d block of Q's tree factor for every tree leaf at
+// off_m[0].
+static hipError_t tree_run(hipStream_t st, const TreePlan& p, int d, char* base, double* R, bool want_q) {
+  const int64_t dd = (int64_t)d * d;
+  const unsigned ddblocks = (unsigned)((dd + 255) / 256);
+  const int levels = (int)p.pairs.size();
+  for (int l = 0; l < levels; ++l) {
+    const int np = p.pairs[l];
+    double* rin = reinterpret_cast<double*>(base + p.off_r[l]);
+    double* rout = reinterpret_cast<double*>(base + p.off_r[l + 1]);
+    double* node = reinterpret_cast<double*>(base + p.off_node[l]);
+    double* ntau = reinterpret_cast<double*>(base + p.off_ntau[l]);
+    double* nt = reinterpret_cast<double*>(base + p.off_nt[l]);
+    double* ntbig = reinterpret_cast<double*>(base + p.off_ntbig[l]);
+    double* ngram = reinterpret_cast<double*>(base + p.off_ngram[l]);
+    const QrShape ns = qr_shape<double>(2 * d, 2 * d, np, d, true);
+    LR_TRY(launch_copy<double>(st, rin, node, (int64_t)np * 2 * dd));  // pairs are adjacent in rin
+    LR_TRY(batched_qr<double>(st, node, 2 * dd, ns, ntau, nt, ntbig, ngram));
+    hipLaunchKernelGGL(extract_r_kernel<double>, dim3(ddblocks, np), dim3(256), 0, st, node, 2 * dd, d, d, rout, np);
+    LR_TRY(hipGetLastError());
+    if (p.count[l] % 2 == 1)
+      LR_TRY(launch_copy<double>(st, rin + (int64_t)(p.count[l] - 1) * dd, rout + (int64_t)np * dd, dd));
+  }
+  // Root: R with diag >= 0, and the root block of Q's tree factor.
+  double* rroot = reinterpret_cast<double*>(base + p.off_r[levels]);
+  double* mroot = reinterpret_cast<double*>(base + p.off_m[levels]);
+  hipLaunchKernelGGL(finalize_r_kernel, dim3(ddblocks), dim3(256), 0, st, rroot, R, mroot, d);
+  LR_TRY(hipGetLastError());
+  if (!want_q) return hipSuccess;
+  // Eq. (4): push the d x d blocks down the tree.
+  for (int l = levels - 1; l >= 0; --l) {
+    const int np = p.pairs[l];
+    double* mup = reinterpret_cast<double*>(base + p.off_m[l + 1]);
+    double* mdn = reinterpret_cast<double*>(base + p.off_m[l]);
+    double* node = reinterpret_cast<double*>(base + p.off_node[l]);
+    double* ntbig = reinterpret_cast<double*>(base + p.off_ntbig[l]);
+    const QrShape ns = qr_shape<double>(2 * d, 2 * d, np, d, true);
+    // [M_up[k]; 0] into the pair slot (2k, 2k+1) of this level
+    const unsigned b2 = (unsigned)((2 * dd + 255) / 256);
+    hipLaunchKernelGGL(init_qblock_kernel<double>, dim3(b2, np), dim3(256), 0, st, mup, mdn, 2 * dd, 2 * d, 2 * d,
+                       np, d);
+    LR_TRY(hipGetLastError());
+    LR_TRY(batched_apply_q<double>(st, node, 2 * dd, mdn, 2 * dd, ns, ntbig));
+    if (p.count[l] % 2 == 1)
+      LR_TRY(launch_copy<double>(st, mup + (int64_t)np * dd, mdn + (int64_t)(p.count[l] - 1) * dd, dd));
+  }
+  return hipSuccess;
+}
+
 struct TsqrPlan {
   int64_t n;
   int d, leaf_rows, nleaf, m_last;
-  std::vector<int> count;  // R factors per level (level 0 = leaves)
-  std::vector<int> pairs;  // nodes per tree level
-  // offsets into the workspace
   size_t off_work, off_tau, off_t, off_tbig, off_gram;
-  std::vector<size_t> off_r, off_m, off_node, off_ntau, off_nt, off_ntbig, off_ngram;
+  TreePlan tree;
   size_t total;
 };
 
@@ -1115,46 +1212,13 @@ static TsqrPlan make_plan(int64_t n, int d, int leaf_rows) {
   off = align256(off + (size_t)n_outer(d) * p.nleaf * blk * sizeof(T));
   p.off_gram = off;
   off = align256(off + (size_t)p.nleaf * blk * sizeof(T));
-  int c = p.nleaf;
-  p.count.push_back(c);
-  while (c > 1) {
-    p.pairs.push_back(c / 2);
-    c = (c + 1) / 2;
-    p.count.push_back(c);
-  }
-  const size_t dd = (size_t)d * d * sizeof(double);
-  for (size_t l = 0; l < p.count.size(); ++l) {
-    p.off_r.push_back(off);
-    off = align256(off + (size_t)p.count[l] * dd);
-    p.off_m.push_back(off);
-    off = align256(off + (size_t)p.count[l] * dd);
-  }
-  for (size_t l = 0; l < p.pairs.size(); ++l) {
-    QrShape ns = qr_shape<double>(2 * d, 2 * d, p.pairs[l], d, true);
-    p.off_node.push_back(off);
-    off = align256(off + (size_t)p.pairs[l] * 2 * dd);
-    p.off_ntau.push_back(off);
-    off = align256(off + (size_t)p.pairs[l] * d * sizeof(double));
-    p.off_nt.push_back(off);
-    off = align256(off + (size_t)p.pairs[l] * ns.npanels * ns.nb * ns.nb * sizeof(double));
-    p.off_ntbig.push_back(off);
-    off = align256(off + (size_t)n_outer(d) * p.pairs[l] * blk * sizeof(double));
-    p.off_ngram.push_back(off);
-    off = align256(off + (size_t)p.pairs[l] * blk * sizeof(double));
-  }
-  p.total = off;
+  p.tree = make_tree_plan(p.nleaf, d, off);
+  p.total = p.tree.end;
   return p;
 }
 
 size_t tsqr_workspace(int64_t n, int d, int leaf_rows, bool f64) {
   return f64 ? make_plan<double>(n, d, leaf_rows).total : make_plan<float>(n, d, leaf_rows).total;
-}
-
-template <typename T>
-static hipError_t launch_copy(hipStream_t st, const T* src, T* dst, int64_t count) {
-  if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(copy_kernel<T>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, src, dst, count);
-  return hipGetLastError();
 }
 
 template <typename T>
@@ -1174,57 +1238,16 @@ hipError_t tsqr_run(hipStream_t st, int64_t n, int d, int leaf_rows, const T* Y,
   // Eq. (1): leaf QRs on a working copy of Y.
   LR_TRY(launch_copy<T>(st, Y, work, n * d));
   LR_TRY(batched_qr<T>(st, work, lstride, ls, tau, tm, tbig, gram));
-  double* r0 = reinterpret_cast<double*>(base + p.off_r[0]);
+  double* r0 = reinterpret_cast<double*>(base + p.tree.off_r[0]);
   hipLaunchKernelGGL(extract_r_kernel<T>, dim3(ddblocks, p.nleaf), dim3(256), 0, st, work, lstride, d, d, r0,
                      p.nleaf);
   LR_TRY(hipGetLastError());
-
-  // Eq. (2)-(3): pairwise QR of stacked R factors, level by level.
-  const int levels = (int)p.pairs.size();
-  for (int l = 0; l < levels; ++l) {
-    const int np = p.pairs[l];
-    double* rin = reinterpret_cast<double*>(base + p.off_r[l]);
-    double* rout = reinterpret_cast<double*>(base + p.off_r[l + 1]);
-    double* node = reinterpret_cast<double*>(base + p.off_node[l]);
-    double* ntau = reinterpret_cast<double*>(base + p.off_ntau[l]);
-    double* nt = reinterpret_cast<double*>(base + p.off_nt[l]);
-    double* ntbig = reinterpret_cast<double*>(base + p.off_ntbig[l]);
-    double* ngram = reinterpret_cast<double*>(base + p.off_ngram[l]);
-    const QrShape ns = qr_shape<double>(2 * d, 2 * d, np, d, true);
-    LR_TRY(launch_copy<double>(st, rin, node, (int64_t)np * 2 * dd));  // pairs are adjacent in rin
-    LR_TRY(batched_qr<double>(st, node, 2 * dd, ns, ntau, nt, ntbig, ngram));
-    hipLaunchKernelGGL(extract_r_kernel<double>, dim3(ddblocks, np), dim3(256), 0, st, node, 2 * dd, d, d, rout, np);
-    LR_TRY(hipGetLastError());
-    if (p.count[l] % 2 == 1)
-      LR_TRY(launch_copy<double>(st, rin + (int64_t)(p.count[l] - 1) * dd, rout + (int64_t)np * dd, dd));
-  }
-
-  // Root: R with diag >= 0, and the root block of Q's tree factor.
-  double* rroot = reinterpret_cast<double*>(base + p.off_r[levels]);
-  double* mroot = reinterpret_cast<double*>(base + p.off_m[levels]);
-  hipLaunchKernelGGL(finalize_r_kernel, dim3(ddblocks), dim3(256), 0, st, rroot, R, mroot, d);
-  LR_TRY(hipGetLastError());
-
-  // Eq. (4): push the d x d blocks down the tree.
-  for (int l = levels - 1; l >= 0; --l) {
-    const int np = p.pairs[l];
-    double* mup = reinterpret_cast<double*>(base + p.off_m[l + 1]);
-    double* mdn = reinterpret_cast<double*>(base + p.off_m[l]);
-    double* node = reinterpret_cast<double*>(base + p.off_node[l]);
-    double* ntbig = reinterpret_cast<double*>(base + p.off_ntbig[l]);
-    const QrShape ns = qr_shape<double>(2 * d, 2 * d, np, d, true);
-    // [M_up[k]; 0] into the pair slot (2k, 2k+1) of this level
-    const unsigned b2 = (unsigned)((2 * dd + 255) / 256);
-    hipLaunchKernelGGL(init_qblock_kernel<double>, dim3(b2, np), dim3(256), 0, st, mup, mdn, 2 * dd, 2 * d, 2 * d,
-                       np, d);
-    LR_TRY(hipGetLastError());
-    LR_TRY(batched_apply_q<double>(st, node, 2 * dd, mdn, 2 * dd, ns, ntbig));
-    if (p.count[l] % 2 == 1)
-      LR_TRY(launch_copy<double>(st, mup + (int64_t)np * dd, mdn + (int64_t)(p.count[l] - 1) * dd, dd));
-  }
+  // Eq. (2)-(4) over the leaf R factors; without Q only R is wanted
+  LR_TRY(tree_run(st, p.tree, d, base, R, Q != nullptr));
+  if (Q == nullptr) return hipSuccess;
 
   // Leaves: Q rows = Q_leaf [M_leaf; 0].
-  double* m0 = reinterpret_cast<double*>(base + p.off_m[0]);
+  double* m0 = reinterpret_cast<double*>(base + p.tree.off_m[0]);
   const unsigned lb = (unsigned)(((int64_t)leaf_rows * d + 255) / 256);
   hipLaunchKernelGGL(init_qblock_kernel<T>, dim3(lb, p.nleaf), dim3(256), 0, st, m0, Q, lstride, leaf_rows,
                      p.m_last, p.nleaf, d);
@@ -1233,6 +1256,174 @@ hipError_t tsqr_run(hipStream_t st, int64_t n, int d, int leaf_rows, const T* Y,
   return hipSuccess;
 }
 
+// ------------------------------------------------------------------ sequential groups (Eq. 5)
+//
+// Leaves are taken in groups of g consecutive blocks. Inside a group the QR
+// runs in sequence: the first block's QR, then for t = 1 .. g-1 the QR of the
+// previous R stacked on block t, [R_{t-1}; K_t] ((d + L) x d), in the working
+// precision. Every group runs its step t at once (one batched QR per step), the
+// groups' last R factors go through the binary tree of Eq. (2)-(4), and Q is
+// pushed back: Q_t [M_t; 0] gives the rows of block t (bottom L rows) and the
+// block M_{t-1} for the step before (top d rows). g = 1 is the binary tree
+// alone; g = the number of blocks is the fully sequential scheme.
+
+// dst[b] = [upper(top d x d of prev[b]); Y rows of block (b g + t)] ((d + L) x d).
+template <typename T>
+__global__ void stack_step_kernel(const T* __restrict__ prev, int64_t pstride, const T* __restrict__ Y, int64_t L,
+                                  int g, int t, int d, T* __restrict__ dst, int64_t dstride) {
+  const int b = blockIdx.y;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t rows = d + L;
+  if (idx >= rows * d) return;
+  const int64_t i = idx / d;
+  const int j = (int)(idx % d);
+  T v;
+  if (i < d)
+    v = (j >= i) ? prev[(int64_t)b * pstride + i * d + j] : (T)0;
+  else
+    v = Y[(((int64_t)b * g + t) * L + (i - d)) * d + j];
+  dst[(int64_t)b * dstride + idx] = v;
+}
+
+// M[b] (double, d x d) = top d x d block of src[b]; rows of block (b g + t) of
+// Q = the bottom L rows of src[b].
+template <typename T>
+__global__ void split_step_kernel(const T* __restrict__ src, int64_t sstride, int64_t L, int g, int t, int d,
+                                  double* __restrict__ M, T* __restrict__ Q) {
+  const int b = blockIdx.y;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (d + L) * d) return;
+  const int64_t i = idx / d;
+  const int j = (int)(idx % d);
+  const T v = src[(int64_t)b * sstride + idx];
+  if (i < d)
+    M[(int64_t)b * d * d + idx] = (double)v;
+  else
+    Q[(((int64_t)b * g + t) * L + (i - d)) * d + j] = v;
+}
+
+struct DominoPlan {
+  int d, L, nleaf, g, groups;
+  size_t off_work, off_tau, off_t, off_tbig0, off_gram, off_mstep, off_qb;
+  std::vector<size_t> off_step, off_stbig;  // steps t = 1 .. g-1
+  TreePlan tree;
+  size_t total;
+};
+
+template <typename T>
+static DominoPlan make_domino_plan(int64_t n, int d, int L, int g) {
+  DominoPlan p;
+  p.d = d;
+  p.L = L;
+  p.nleaf = (int)(n / L);
+  p.g = g;
+  p.groups = p.nleaf / g;
+  const QrShape s0 = qr_shape<T>(L, L, p.groups, d);
+  const QrShape s1 = qr_shape<T>(d + L, d + L, p.groups, d);
+  const int tsz = s0.npanels * s0.nb * s0.nb > s1.npanels * s1.nb * s1.nb ? s0.npanels * s0.nb * s0.nb
+                                                                          : s1.npanels * s1.nb * s1.nb;
+  const size_t blk = (size_t)kOuter * kOuter;
+  const size_t tbig_bytes = (size_t)n_outer(d) * p.groups * blk * sizeof(T);
+  size_t off = 0;
+  p.off_work = off;
+  off = align256(off + (size_t)n * d * sizeof(T));
+  p.off_tau = off;
+  off = align256(off + (size_t)p.groups * d * sizeof(T));
+  p.off_t = off;
+  off = align256(off + (size_t)p.groups * tsz * sizeof(T));
+  p.off_gram = off;
+  off = align256(off + (size_t)p.groups * blk * sizeof(T));
+  p.off_tbig0 = off;
+  off = align256(off + tbig_bytes);
+  for (int t = 1; t < g; ++t) {
+    p.off_step.push_back(off);
+    off = align256(off + (size_t)p.groups * (d + L) * d * sizeof(T));
+    p.off_stbig.push_back(off);
+    off = align256(off + tbig_bytes);
+  }
+  p.off_mstep = off;
+  off = align256(off + (size_t)p.groups * d * d * sizeof(double));
+  p.off_qb = off;
+  off = align256(off + (size_t)p.groups * (d + L) * d * sizeof(T));
+  p.tree = make_tree_plan(p.groups, d, off);
+  p.total = p.tree.end;
+  return p;
+}
+
+size_t tsqr_domino_workspace(int64_t n, int d, int leaf_rows, int group, bool f64) {
+  return f64 ? make_domino_plan<double>(n, d, leaf_rows, group).total
+             : make_domino_plan<float>(n, d, leaf_rows, group).total;
+}
+
+template <typename T>
+hipError_t tsqr_domino_run(hipStream_t st, int64_t n, int d, int L, int g, const T* Y, T* Q, double* R, void* ws) {
+  const DominoPlan p = make_domino_plan<T>(n, d, L, g);
+  char* base = static_cast<char*>(ws);
+  T* work = reinterpret_cast<T*>(base + p.off_work);
+  T* tau = reinterpret_cast<T*>(base + p.off_tau);
+  T* tm = reinterpret_cast<T*>(base + p.off_t);
+  T* gram = reinterpret_cast<T*>(base + p.off_gram);
+  T* tbig0 = reinterpret_cast<T*>(base + p.off_tbig0);
+  const int G = p.groups;
+  const int64_t dd = (int64_t)d * d;
+  const int64_t gstride = (int64_t)g * L * d;  // first block of each group in work / Y / Q
+  const int64_t sstride = (int64_t)(d + L) * d;
+  const QrShape s0 = qr_shape<T>(L, L, G, d);
+  const QrShape s1 = qr_shape<T>(d + L, d + L, G, d);
+  const unsigned ddblocks = (unsigned)((dd + 255) / 256);
+  const unsigned sblocks = (unsigned)((sstride + 255) / 256);
+
+  // step 0: the first block of every group
+  LR_TRY(launch_copy<T>(st, Y, work, n * d));
+  LR_TRY(batched_qr<T>(st, work, gstride, s0, tau, tm, tbig0, gram));
+  // steps 1 .. g-1: [R_{t-1}; K_t]
+  const T* prev = work;
+  int64_t pstride = gstride;
+  for (int t = 1; t < g; ++t) {
+    T* S = reinterpret_cast<T*>(base + p.off_step[t - 1]);
+    T* tb = reinterpret_cast<T*>(base + p.off_stbig[t - 1]);
+    hipLaunchKernelGGL(stack_step_kernel<T>, dim3(sblocks, G), dim3(256), 0, st, prev, pstride, Y, (int64_t)L, g, t,
+                       d, S, sstride);
+    LR_TRY(hipGetLastError());
+    LR_TRY(batched_qr<T>(st, S, sstride, s1, tau, tm, tb, gram));
+    prev = S;
+    pstride = sstride;
+  }
+  double* r0 = reinterpret_cast<double*>(base + p.tree.off_r[0]);
+  hipLaunchKernelGGL(extract_r_kernel<T>, dim3(ddblocks, G), dim3(256), 0, st, prev, pstride, d, d, r0, G);
+  LR_TRY(hipGetLastError());
+  LR_TRY(tree_run(st, p.tree, d, base, R, Q != nullptr));
+  if (Q == nullptr) return hipSuccess;
+
+  // Q back down every group, starting from the tree's block for the group
+  double* mcur = reinterpret_cast<double*>(base + p.tree.off_m[0]);
+  double* mnext = reinterpret_cast<double*>(base + p.off_mstep);
+  T* qb = reinterpret_cast<T*>(base + p.off_qb);
+  for (int t = g - 1; t >= 1; --t) {
+    const T* S = reinterpret_cast<const T*>(base + p.off_step[t - 1]);
+    const T* tb = reinterpret_cast<const T*>(base + p.off_stbig[t - 1]);
+    hipLaunchKernelGGL(init_qblock_kernel<T>, dim3(sblocks, G), dim3(256), 0, st, mcur, qb, sstride, d + L, d + L, G,
+                       d);
+    LR_TRY(hipGetLastError());
+    LR_TRY(batched_apply_q<T>(st, S, sstride, qb, sstride, s1, tb));
+    hipLaunchKernelGGL(split_step_kernel<T>, dim3(sblocks, G), dim3(256), 0, st, qb, sstride, (int64_t)L, g, t, d,
+                       mnext, Q);
+    LR_TRY(hipGetLastError());
+    double* tmp = mcur;
+    mcur = mnext;
+    mnext = tmp;
+  }
+  // the first block of every group: Q rows = Q_0 [M_0; 0]
+  const unsigned lb = (unsigned)(((int64_t)L * d + 255) / 256);
+  hipLaunchKernelGGL(init_qblock_kernel<T>, dim3(lb, G), dim3(256), 0, st, mcur, Q, gstride, L, L, G, d);
+  LR_TRY(hipGetLastError());
+  LR_TRY(batched_apply_q<T>(st, work, gstride, Q, gstride, s0, tbig0));
+  return hipSuccess;
+}
+
+template hipError_t tsqr_domino_run<float>(hipStream_t, int64_t, int, int, int, const float*, float*, double*, void*);
+template hipError_t tsqr_domino_run<double>(hipStream_t, int64_t, int, int, int, const double*, double*, double*,
+                                            void*);
 template hipError_t tsqr_run<float>(hipStream_t, int64_t, int, int, const float*, float*, double*, void*);
 template hipError_t tsqr_run<double>(hipStream_t, int64_t, int, int, const double*, double*, double*, void*);
 

@@ -193,3 +193,19 @@ def test_projection_and_psd_validation():
     assert lib.lr_psd_part(None, 64, FAKE, FAKE, ws, 1 << 30) == L.LR_ERR_ARG  # Bplus aliases B
     assert lib.lr_psd_part(None, 64, FAKE, ctypes.c_void_p(0x30000), ws, 8) == L.LR_ERR_WORKSPACE
     assert lib.lr_psd_part_workspace_bytes(64) >= 3 * 64 * 64 * 8
+
+
+def test_tsqr_tree_validation():
+    lib = L.lib()
+    ws = ctypes.c_void_p(0x100000)
+    t = lambda n=4096, d=64, leaf=512, group=2, prec=L.LR_PREC_F32, q=FAKE, wsb=1 << 40: lib.lr_tsqr_tree(
+        None, n, d, leaf, group, prec, FAKE, q, FAKE, ws, wsb)
+    assert t(group=0) == L.LR_ERR_SHAPE
+    assert t(group=3) == L.LR_ERR_SHAPE           # 8 blocks are not a multiple of 3
+    assert t(n=4100) == L.LR_ERR_SHAPE            # groups need whole blocks
+    assert t(leaf=8192, n=16384, d=64) == L.LR_ERR_SHAPE  # d + leaf_rows > 8192 in a sequential step
+    assert t(wsb=64) == L.LR_ERR_WORKSPACE
+    assert t(group=1, n=4160, wsb=64) == L.LR_ERR_WORKSPACE  # the binary tree takes a short last block
+    assert lib.lr_tsqr_tree_workspace_bytes(4096, 64, 512, 1, L.LR_PREC_F32) == \
+        lib.lr_tsqr_workspace_bytes(4096, 64, 512, L.LR_PREC_F32)
+    assert lib.lr_tsqr_tree_workspace_bytes(4096, 64, 512, 3, L.LR_PREC_F32) == 0

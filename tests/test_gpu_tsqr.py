@@ -133,3 +133,36 @@ def test_tsqr_largest_d_matches_unique_qr(prec, n, d, leaf):
     else:
         tol = 20 * math.sqrt(n) * u
         assert orth <= tol and back <= tol and err_r <= 4 * tol and err_q <= 4 * tol
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("group", [1, 2, 4, 8])
+def test_tsqr_tree_groups_match_oracle(prec, group):
+    """lr_tsqr_tree: groups of blocks run in sequence (Eq. 5) under the binary
+    tree, against the oracle's grouped scheme (group = 1: the binary tree;
+    group = 8 = the number of blocks: fully sequential), with and without Q."""
+    dev = device()
+    a = api()
+    n, d, leaf = 8 * 512, 64, 512
+    y = _gauss_y(n, d, 31 * group)
+    if prec == "f32":
+        y = y.astype(np.float32).astype(np.float64)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    Y = to_dev(y, dt, dev)
+    note(f"tsqr tree n={n} d={d} leaf={leaf} group={group} prec={prec}")
+    Q, R = a.tsqr_tree(Y, leaf, prec, group=group)
+    _, R_only = a.tsqr_tree(Y, leaf, prec, group=group, want_q=False)
+    torch.cuda.synchronize()
+    qo, ro = oqr.tsqr_grouped(y, leaf, group)
+    orth, back, r = _props(Y, Q, R)
+    u = U64 if prec == "f64" else U32
+    err_r = np.abs(r - ro).max() / np.abs(ro).max()
+    err_q = np.abs(Q.double().cpu().numpy() - qo).max()
+    note(f"  R rel {err_r:.2e} Q {err_q:.2e} orth {orth:.2e} back {back:.2e}")
+    assert np.all(np.tril(r, -1) == 0.0) and np.all(np.diag(r) >= 0)
+    assert orth <= 50 * math.sqrt(n) * u and back <= 50 * math.sqrt(n) * u
+    assert torch.equal(R, R_only)  # the same factorisation, Q never formed
+    if prec == "f64":
+        assert err_r <= 1e-12 and err_q <= 1e-11
+    else:
+        assert err_r <= 80 * math.sqrt(n) * u and err_q <= 80 * math.sqrt(n) * u
