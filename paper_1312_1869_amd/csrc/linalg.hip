@@ -396,16 +396,146 @@ __global__ void reduce_partials_kernel(const double* __restrict__ partial, int64
   out[idx] = scale * s;
 }
 
+// out[idx] = scale * sum_c partial[c * count + idx] with one wave per output:
+// lane l sums partials l, l + 64, ... in order, then a fixed butterfly adds the
+// lanes (the same order on every call).
+__global__ __launch_bounds__(256) void reduce_partials_wave_kernel(const double* __restrict__ partial, int64_t nchunk,
+                                                                   int64_t count, double scale,
+                                                                   double* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (idx >= count) return;
+  double s = 0.0;
+  for (int64_t c = lane; c < nchunk; c += 64) s += partial[c * count + idx];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) out[idx] = scale * s;
+}
+
+static hipError_t launch_reduce_partials(hipStream_t st, const double* partial, int64_t nch, int64_t count,
+                                         double scale, double* out) {
+  if (nch >= 128 && count < 65536)
+    hipLaunchKernelGGL(reduce_partials_wave_kernel, dim3((unsigned)((count + 3) / 4)), dim3(256), 0, st, partial, nch,
+                       count, scale, out);
+  else
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, partial, nch,
+                       count, scale, out);
+  return hipGetLastError();
+}
+
 static int64_t tn_chunk(int64_t n) {
   int64_t chunk = 4096;
   while ((n + chunk - 1) / chunk > 64) chunk *= 2;
   return chunk;
 }
 
+// Skinny products (row-major X n x M, M <= 1024, against row-major Y n x N,
+// N <= 16: Z = Q^T A, Q^T y): one workgroup per chunk of rows, every thread
+// owns the columns t, t + 256, ... of X against all N columns of Y, whose row
+// is the same for the whole workgroup (scalar loads). Products of float inputs
+// are exact in float64 and are summed in float64.
+constexpr int kSkinnyMaxM = 1024;
+constexpr int kSkinnyMaxN = 16;
+static int64_t skinny_chunk(int64_t n) {
+  int64_t chunk = 256;
+  while ((n + chunk - 1) / chunk > 1024) chunk *= 2;
+  return chunk;
+}
+
 size_t tn_workspace(int64_t n, int M, int N) {
   const int64_t chunk = tn_chunk(n);
   const int64_t nch = (n + chunk - 1) / chunk;
-  return (size_t)(nch < 1 ? 1 : nch) * (size_t)M * (size_t)N * sizeof(double);
+  size_t b = (size_t)(nch < 1 ? 1 : nch) * (size_t)M * (size_t)N * sizeof(double);
+  // room for a skinny product of any M' <= M, N' <= N as well
+  const int ms = M < kSkinnyMaxM ? M : kSkinnyMaxM;
+  const int nsk = N < kSkinnyMaxN ? N : kSkinnyMaxN;
+  const int64_t ns = (n + skinny_chunk(n) - 1) / skinny_chunk(n);
+  const size_t bs = (size_t)(ns < 1 ? 1 : ns) * (size_t)ms * (size_t)nsk * sizeof(double);
+  return bs > b ? bs : b;
+}
+
+template <typename RX, int CPM, int NN>
+__global__ __launch_bounds__(256) void gemm_tn_skinny_kernel(int64_t n, int64_t chunk, int M, int N,
+                                                             const RX* __restrict__ X, int64_t ldx,
+                                                             const RX* __restrict__ Y, int64_t ldy,
+                                                             double* __restrict__ partial) {
+  // the Y rows of the current 256-row tile, converted to float64 once (thread
+  // t converts row t); every thread then reads each row as a broadcast
+  __shared__ double ytile[256][NN];
+  const int t = threadIdx.x;
+  const int64_t rbeg = (int64_t)blockIdx.x * chunk;
+  const int64_t rend = rbeg + chunk < n ? rbeg + chunk : n;
+  double acc[CPM][NN];
+#pragma unroll
+  for (int c = 0; c < CPM; ++c)
+#pragma unroll
+    for (int k = 0; k < NN; ++k) acc[c][k] = 0.0;
+  for (int64_t r0 = rbeg; r0 < rend; r0 += 256) {
+    const int rows = rend - r0 < 256 ? (int)(rend - r0) : 256;
+    {
+      const int64_t r = r0 + t;
+#pragma unroll
+      for (int k = 0; k < NN; ++k) ytile[t][k] = (t < rows && k < N) ? (double)Y[r * ldy + k] : 0.0;
+    }
+    __syncthreads();
+    // eight rows of X per trip, all loads issued before the products
+    constexpr int kRows = 8;
+    for (int i0 = 0; i0 < rows; i0 += kRows) {
+      RX qv[kRows][CPM];
+#pragma unroll
+      for (int u = 0; u < kRows; ++u) {
+        const int64_t r = r0 + i0 + u;
+#pragma unroll
+        for (int c = 0; c < CPM; ++c) {
+          const int col = t + 256 * c;
+          qv[u][c] = (i0 + u < rows && col < M) ? X[r * ldx + col] : (RX)0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kRows; ++u) {
+        const int i = i0 + u < rows ? i0 + u : rows - 1;  // rows past the tile add q = 0
+#pragma unroll
+        for (int c = 0; c < CPM; ++c) {
+          const double q = (double)qv[u][c];
+#pragma unroll
+          for (int k = 0; k < NN; ++k) acc[c][k] = __builtin_fma(q, ytile[i][k], acc[c][k]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double* out = partial + (int64_t)blockIdx.x * M * N;
+#pragma unroll
+  for (int c = 0; c < CPM; ++c) {
+    const int col = t + 256 * c;
+    if (col < M) {
+#pragma unroll
+      for (int k = 0; k < NN; ++k)
+        if (k < N) out[(int64_t)col * N + k] = acc[c][k];
+    }
+  }
+}
+
+template <typename RX, int CPM>
+static hipError_t launch_skinny_cpm(hipStream_t st, int64_t n, int64_t chunk, int64_t nch, int M, int N,
+                                    const RX* X, int64_t ldx, const RX* Y, int64_t ldy, double* partial) {
+  const dim3 g((unsigned)nch), b(256);
+  if (N <= 1)
+    hipLaunchKernelGGL((gemm_tn_skinny_kernel<RX, CPM, 1>), g, b, 0, st, n, chunk, M, N, X, ldx, Y, ldy, partial);
+  else if (N <= 4)
+    hipLaunchKernelGGL((gemm_tn_skinny_kernel<RX, CPM, 4>), g, b, 0, st, n, chunk, M, N, X, ldx, Y, ldy, partial);
+  else if (N <= 8)
+    hipLaunchKernelGGL((gemm_tn_skinny_kernel<RX, CPM, 8>), g, b, 0, st, n, chunk, M, N, X, ldx, Y, ldy, partial);
+  else
+    hipLaunchKernelGGL((gemm_tn_skinny_kernel<RX, CPM, 16>), g, b, 0, st, n, chunk, M, N, X, ldx, Y, ldy, partial);
+  return hipGetLastError();
+}
+
+template <typename RX>
+static hipError_t launch_skinny(hipStream_t st, int64_t n, int64_t chunk, int64_t nch, int M, int N, const RX* X,
+                                int64_t ldx, const RX* Y, int64_t ldy, double* partial) {
+  if (M <= 256) return launch_skinny_cpm<RX, 1>(st, n, chunk, nch, M, N, X, ldx, Y, ldy, partial);
+  if (M <= 512) return launch_skinny_cpm<RX, 2>(st, n, chunk, nch, M, N, X, ldx, Y, ldy, partial);
+  return launch_skinny_cpm<RX, 4>(st, n, chunk, nch, M, N, X, ldx, Y, ldy, partial);
 }
 
 hipError_t launch_gemm_tn(hipStream_t st, int64_t n, int M, int N, const TnOperand& X, const TnOperand& Y,
@@ -433,6 +563,19 @@ hipError_t launch_gemm_tn(hipStream_t st, int64_t n, int M, int N, const TnOpera
     hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, partial,
                        nch, count, x_scale, out);
     return hipGetLastError();
+  }
+  // skinny real x real products (exact float64 products and sums either way)
+  if (X.kind == 0 && Y.kind == 0 && X.dtype == Y.dtype && X.dtype != 2 && M <= kSkinnyMaxM && N <= kSkinnyMaxN &&
+      (f64 || X.dtype == 1)) {
+    const int64_t sc = skinny_chunk(n);
+    const int64_t ns = (n + sc - 1) / sc;
+    hipError_t e = X.dtype == 0
+                       ? launch_skinny<double>(st, n, sc, ns, M, N, static_cast<const double*>(X.ptr), X.ld,
+                                               static_cast<const double*>(Y.ptr), Y.ld, partial)
+                       : launch_skinny<float>(st, n, sc, ns, M, N, static_cast<const float*>(X.ptr), X.ld,
+                                              static_cast<const float*>(Y.ptr), Y.ld, partial);
+    if (e != hipSuccess) return e;
+    return launch_reduce_partials(st, partial, ns, count, x_scale, out);
   }
   dim3 grid((M + 63) / 64, (N + 63) / 64, (unsigned)nch);
   if (f64)
