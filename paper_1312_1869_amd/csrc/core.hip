@@ -162,11 +162,14 @@ __global__ __launch_bounds__(TPB) void lu_panel_kernel(int d, double* A, int k0,
 
 constexpr int kLuCols = 64;
 
-__global__ __launch_bounds__(256) void lu_update_kernel(int d, double* A, int k0, const int32_t* __restrict__ piv,
-                                                        const int32_t* __restrict__ info) {
+// After the panel at k0: the panel's row exchanges on every other column
+// block, and on the blocks right of the panel U12 = L11^{-1} A12 (unit lower,
+// one column per thread, solved through LDS and written back). The rank-nb
+// update of A22 follows in lu_gemm_kernel.
+__global__ __launch_bounds__(256) void lu_swap_solve_kernel(int d, double* A, int k0, const int32_t* __restrict__ piv,
+                                                            const int32_t* __restrict__ info) {
   __shared__ double L11[kPanel][kPanel];
   __shared__ double U12[kPanel][kLuCols];
-  __shared__ double L21[64][kPanel];
   if (*info != 0) return;
   const int t = threadIdx.x;
   const int nb = min(kPanel, d - k0);
@@ -203,7 +206,6 @@ __global__ __launch_bounds__(256) void lu_update_kernel(int d, double* A, int k0
     L11[i][j] = (i < nb && j < nb) ? A[(int64_t)(k0 + i) * d + k0 + j] : 0.0;
   }
   __syncthreads();
-  // U12 = L11^{-1} A12 (unit lower), one column per thread, solved in LDS
   if (t < kLuCols) {
     for (int i = 0; i < kPanel; ++i) {
       double s = (col_ok && i < nb) ? A[(int64_t)(k0 + i) * d + col] : 0.0;
@@ -212,24 +214,34 @@ __global__ __launch_bounds__(256) void lu_update_kernel(int d, double* A, int k0
       if (col_ok && i < nb) A[(int64_t)(k0 + i) * d + col] = s;
     }
   }
+}
+
+// A22 -= L21 U12 for the trailing matrix right of and below the panel: one
+// workgroup per 64 x 64 tile, L21 and U12 staged through LDS.
+__global__ __launch_bounds__(256) void lu_gemm_kernel(int d, double* A, int k0, const int32_t* __restrict__ info) {
+  __shared__ double L21[64][kPanel + 1];
+  __shared__ double U12[kPanel][64];
+  if (*info != 0) return;
+  const int t = threadIdx.x;
+  const int nb = min(kPanel, d - k0);
+  const int kend = k0 + nb;
+  const int c0 = kend + blockIdx.x * 64;
+  const int r0 = kend + blockIdx.y * 64;
+  for (int e = t; e < 64 * kPanel; e += 256) {
+    const int i = e / kPanel, q = e % kPanel;
+    L21[i][q] = (r0 + i < d && q < nb) ? A[(int64_t)(r0 + i) * d + k0 + q] : 0.0;
+    const int qq = e / 64, j = e % 64;
+    U12[qq][j] = (c0 + j < d && qq < nb) ? A[(int64_t)(k0 + qq) * d + c0 + j] : 0.0;
+  }
   __syncthreads();
-  // A22 -= L21 U12 over rows kend .. d-1 (4 row groups of the 64-row chunks)
-  const int rg = t >> 6;
-  for (int r0 = kend; r0 < d; r0 += 64) {
-    for (int e = t; e < 64 * kPanel; e += 256) {
-      const int i = e / kPanel, q = e % kPanel;
-      L21[i][q] = (r0 + i < d && q < nb) ? A[(int64_t)(r0 + i) * d + k0 + q] : 0.0;
-    }
-    __syncthreads();
-    if (col_ok) {
-      for (int i = rg; i < 64 && r0 + i < d; i += 4) {
-        double s = 0.0;
+  const int cl = t & 63;
+  const int col = c0 + cl;
+  if (col >= d) return;
+  for (int i = t >> 6; i < 64 && r0 + i < d; i += 4) {
+    double s = 0.0;
 #pragma unroll
-        for (int q = 0; q < kPanel; ++q) s += L21[i][q] * U12[q][cl];
-        A[(int64_t)(r0 + i) * d + col] -= s;
-      }
-    }
-    __syncthreads();
+    for (int q = 0; q < kPanel; ++q) s += L21[i][q] * U12[q][cl];
+    A[(int64_t)(r0 + i) * d + col] -= s;
   }
 }
 
@@ -405,8 +417,11 @@ hipError_t launch_core(hipStream_t st, int64_t n, int d, const double* F, const 
                          logdet);
     }
     const int kend = min(k0 + kPanel, d);
-    const int nblk = (k0 + kLuCols - 1) / kLuCols + (d - kend + kLuCols - 1) / kLuCols;
-    if (nblk > 0) hipLaunchKernelGGL(lu_update_kernel, dim3(nblk), dim3(256), 0, st, d, Flu, k0, piv, info);
+    const int nright = (d - kend + kLuCols - 1) / kLuCols;
+    const int nblk = (k0 + kLuCols - 1) / kLuCols + nright;
+    if (nblk > 0) hipLaunchKernelGGL(lu_swap_solve_kernel, dim3(nblk), dim3(256), 0, st, d, Flu, k0, piv, info);
+    const int ntile = (d - kend + 63) / 64;
+    if (ntile > 0) hipLaunchKernelGGL(lu_gemm_kernel, dim3(ntile, ntile), dim3(256), 0, st, d, Flu, k0, info);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // C = F^{-1} R^T: column c of R^T is row c of R
