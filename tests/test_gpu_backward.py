@@ -393,3 +393,25 @@ def test_c4_full_fp64_gradient():
     # parity bars to that
     assert abs(ll0 - ex["c4_loglik_exact"]) <= 1e-11 * abs(ex["c4_loglik_exact"]) + 1e-10 * abs(gold["loglik"])
     assert np.all(np.abs(g - g_ex) <= 3e-6 * np.abs(g_ex) + bar)
+
+
+def test_c5_full_fused_forward_backward_stagewise():
+    """The largest workload at full size (n = 2^20, d = 1024, SE, SRHT, FP32,
+    A 2^20 x 16): the fused forward (Y and Y' from one pass) and the backward of
+    <A, K~^{-1} A>, stage-wise against the oracle's gradient formulas fed the
+    GPU's Q (promoted), core factors and Y' (the bar of the other stage-wise
+    checks), and X against the oracle's apply on the same factors. The
+    sketch's own parity at this size is test_gpu_sketch's sampled-row check."""
+    dev = device()
+    w = W.WORKLOADS["C5"]
+    A = W.rhs(w)
+    note(f"C5 full fused forward + backward n={w.n} d={w.d} m={w.m}")
+    r = _gpu_run(w, "f32", dev, A, True, mode=1, abar=A)
+    q = r["Q"]
+    g_st, _ = og.grad_solve(r["x"], w.kernel, w.ell, w.s, w.sigma2, r["om"], q, r["core"], A, A, yprime=r["Yp"])
+    e_st = _rel(r["g"], g_st)
+    x_st = olr.apply(q, r["core"]["L"], A.astype(np.float64), w.sigma2)
+    ex = float(np.abs(r["X"] - x_st).max() / np.abs(x_st).max())
+    note(f"  grad {r['g']} stage-wise {g_st} rel {e_st}; X stage-wise {ex:.2e}")
+    assert np.all(e_st <= _stage_bar(q, 0.0))
+    assert ex <= 1e-5

@@ -273,3 +273,54 @@ def test_omega_t_q_product_against_oracle(prec):
     err = float((np.abs(f - ref) / scale).max())
     note(f"  max |F - Omega^T Q| / (|Omega|^T |Q|) = {err:.3e}")
     assert err <= 520 * 2.0 ** -24
+
+
+def test_c2_full_fp32_against_fp64_path():
+    """The FP32-vs-FP64 workload at full size (n = 65536, D = 3, SE, SRHT
+    d = 256, A 65536 x 8). The FP64 path is pinned to the oracle: sketch rows
+    sampled against the oracle's (SRHT bar), and the oracle's core and apply
+    fed the GPU's FP64 Q and R (1e-10). The FP32 path is compared stage-wise
+    the same way (the C/L bar of test_c3_full_bf16_stagewise) and end to end
+    with the FP64 path, against 4x the distance of the oracle's float32
+    precision model (the GPU's float32 sketch, LAPACK's float32 QR, the float64
+    core and apply) from that path."""
+    dev = device()
+    w = W.WORKLOADS["C2"]
+    x, A, om_np, _, Y64, Q64, R64, sol64 = _forward(w, "f64", dev)
+    assert int(sol64.info.item()) == 0
+    rows = np.concatenate([[0, w.n - 1], np.random.default_rng(5).choice(w.n, 10, replace=False)])
+    y_ref = osk.sketch_rows(x, rows, w.kernel, w.ell, w.s, om_np)
+    from oracle import kernels as okr
+    kabs = np.abs(okr.kernel_matrix(w.kernel, x[rows].astype(np.float64), x.astype(np.float64), w.ell, w.s))
+    sc = kabs.sum(axis=1, keepdims=True) / math.sqrt(w.n)
+    ey = (np.abs(Y64.cpu().numpy()[rows] - y_ref) / sc).max()
+    q64, r64 = Q64.cpu().numpy(), R64.cpu().numpy()
+    ref64 = olr.solve(q64, r64, om_np, w.sigma2, A.astype(np.float64))
+    ex64 = rel_max(sol64.X.cpu().numpy(), ref64["X"])
+    el64 = abs(sol64.logdet.item() - ref64["logdet"]) / abs(ref64["logdet"])
+    note(f"  FP64 path: sampled Y {ey:.2e} of the SRHT scale; stage-wise X {ex64:.2e} logdet {el64:.2e}")
+    assert ey <= 16 * math.log2(w.n) * 2.0 ** -53
+    assert ex64 <= 1e-10 and el64 <= 1e-10
+    x32, A32, _, _, Y32, Q32, R32, sol32 = _forward(w, "f32", dev)
+    assert int(sol32.info.item()) == 0
+    q, r = Q32.double().cpu().numpy(), R32.cpu().numpy()
+    c = olr.core(q, r, om_np, w.sigma2)
+    assert c["info"] == 0
+    kf = float(np.linalg.cond(c["F"]))
+    tol_c = 10.0 * kf * 520 * 2.0 ** -24
+    eC = float(np.abs(sol32.C.cpu().numpy() - c["C"]).max() / np.abs(c["C"]).max())
+    ld = olr.logdet(c["L"], w.n, w.sigma2)
+    el = abs(sol32.logdet.item() - ld) / abs(ld)
+    xr = olr.apply(q, c["L"], A.astype(np.float64), w.sigma2)
+    ex = rel_max(sol32.X.double().cpu().numpy(), xr)
+    note(f"  FP32 stage-wise: C {eC:.2e} logdet {el:.2e} X {ex:.2e} (cond F {kf:.1f}, bar {tol_c:.1e})")
+    assert eC <= tol_c and el <= tol_c
+    assert ex <= 2.0 ** -24 + float(np.linalg.cond(c["S"])) * tol_c
+    mod = _model_forward(x, w, om_np, A, Y32.double().cpu().numpy())
+    x64 = sol64.X.cpu().numpy()
+    d_x = rel_max(sol32.X.double().cpu().numpy(), x64)
+    d_l = abs(sol32.logdet.item() - sol64.logdet.item()) / abs(sol64.logdet.item())
+    m_x = rel_max(mod["X"], x64)
+    m_l = abs(mod["logdet"] - sol64.logdet.item()) / abs(sol64.logdet.item())
+    note(f"  FP32 vs FP64 path: X {d_x:.2e} logdet {d_l:.2e}; float32 model X {m_x:.2e} logdet {m_l:.2e}")
+    assert d_x <= 1e-5 + 4.0 * m_x and d_l <= 1e-8 + 4.0 * m_l
