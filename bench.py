@@ -201,6 +201,32 @@ def grid_rates(torch, api, W, dev, g: int = 16) -> dict:
             "sketch_grid_ms": grid_ms, "single_sketches_ms": single_ms, "loglik_grid_ms": ll_ms}
 
 
+def c5_forward_backward(torch, api, W, dev) -> dict:
+    """The largest workload (n = 2^20, d = 1024, FP32, A 2^20 x 16): the forward
+    with the fused derivative sketch, and the backward of <A, K~^{-1} A>."""
+    w = W.WORKLOADS["C5"]
+    x = torch.from_numpy(W.points(w)).to(dev)
+    A = torch.from_numpy(W.rhs(w)).to(dev)
+    signs, cols = W.srht_draw(w)
+    om = api.Omega.srht(signs, cols, dev)
+    hyp = api.Hyper(w.kernel, w.ell, w.s)
+    stream = torch.cuda.current_stream(dev)
+    state = {}
+
+    def fwd():
+        state["fw"] = api.forward(x, hyp, om, "f32", w.sigma2, A, w.leaf_rows, want_yprime=True)
+
+    def bwd():
+        fw = state["fw"]
+        api.backward(x, hyp, om, "f32", fw.sol, fw.Q, w.sigma2, 1, A, V=A, Yprime=fw.Yprime, R=fw.R)
+
+    f_ms = _event_ms(fwd, 1, torch, stream)
+    b_ms = _event_ms(bwd, 1, torch, stream)
+    out = {"workload": f"C5: n={w.n} SE SRHT d={w.d} m={w.m}, FP32", "forward_fused_ms": f_ms, "backward_ms": b_ms}
+    del state
+    return out
+
+
 def _exact_c4():
     """Exact dense log-likelihood and gradient at the log-likelihood workload,
     as stored by tests/golden/make_exact_reference.py (None if absent)."""
@@ -312,6 +338,9 @@ def main() -> int:
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--with-backward", action="store_true",
+                    help="time forward (with the fused derivative sketch) + hyperparameter backward per step "
+                         "(log-likelihood for one right-hand side, else the adjoint of <A, K~^-1 A>)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FP32 path, SRHT, apply and log-likelihood measurements")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -363,6 +392,18 @@ def main() -> int:
         return api.forward(X, hyp, om_, prec_, w.sigma2, A_, w.leaf_rows, want_yprime=want_yprime)
 
     # ---- warmup and timed steps
+    if args.with_backward:
+        # the float32 log-likelihood at d near the kernel's numerical rank needs
+        # the stabilising shift (its core is indefinite without it)
+        bw_nu = 0.1 * w.sigma2 if (w.m == 1 and prec != "f64") else 0.0
+        bw_mode = 0 if w.m == 1 else 1
+
+        def step(prec_, om_, A_, want_yprime=False):  # noqa: F811
+            fw = api.forward(X, hyp, om_, prec_, w.sigma2, A_, w.leaf_rows, nu=bw_nu, want_yprime=True)
+            api.backward(X, hyp, om_, prec_, fw.sol, fw.Q, w.sigma2, bw_mode, A_, V=None if bw_mode == 0 else A_,
+                         Yprime=fw.Yprime, R=fw.R, nu=bw_nu)
+            return fw
+
     for _ in range(args.warmup):
         step(prec, om, Ad)
     torch.cuda.synchronize()
@@ -420,7 +461,8 @@ def main() -> int:
         "vs_baseline": None, "dtype": prec, "data": "synthetic",
         "config": {"workload": f"{w.name}: n={w.n} D={w.D} {w.kernel} ell={w.ell} s={w.s} sigma2={w.sigma2} "
                                f"{w.omega} d={w.d} m={w.m} leaf_rows={w.leaf_rows}",
-                   "global_batch": w.n, "seq_len": w.d, "parallelism": "single-gpu"},
+                   "global_batch": w.n, "seq_len": w.d, "parallelism": "single-gpu",
+                   "step": "forward + backward" if args.with_backward else "forward"},
         "seconds_per_solve": ms / 1e3, "stages_ms": stage_ms, "algorithmic_flops": flops, "info": info,
         "roofline": roofline,
     }
@@ -497,6 +539,7 @@ def main() -> int:
         result["c1_exact"] = c1_error_vs_exact(torch, api, W, dev)
         result["structured_omega"] = structured_rates(torch, api, W, dev)
         result["hyperparameter_grid"] = grid_rates(torch, api, W, dev)
+        result["c5_forward_backward"] = c5_forward_backward(torch, api, W, dev)
         # blocked-QR shapes on this workload's sketch: the binary tree with and
         # without forming Q, and groups of 2 and 4 blocks run in sequence (Eq. 5)
         Ys, _ = api.sketch(X, hyp, om, prec)
