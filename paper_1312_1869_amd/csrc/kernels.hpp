@@ -14,6 +14,14 @@ hipError_t launch_prep_points(hipStream_t st, const float* X, int64_t n, int D, 
 template <typename T>
 hipError_t launch_sketch_srht(hipStream_t st, int kernel, int D, const T* pts, const int32_t* cols, int64_t n,
                               int d, double scale_out, double nu_c, T* Y, T* Yp, int num_cu);
+// out (d x N, float64) = scale * Omega^T M for an SRHT Omega (signs, cols) and
+// a row-major real M (n x N, leading dimension N), in slabs of S rows
+// (srht_left_slab: the largest slab whose transposed copy fits ws_bytes next
+// to an N x d float64 accumulator; 0 when the product does not fit this path).
+int64_t srht_left_slab(int64_t n, int d, int N, size_t elem, size_t ws_bytes);
+template <typename T>
+hipError_t launch_srht_left(hipStream_t st, int64_t n, int d, const int8_t* signs, const int32_t* cols, const T* M,
+                            int N, double scale, double* out, void* ws, int64_t S);
 // SRHT sketches Y_g (g < ntheta, Y_g = Y + g n d) for a batch of kernels that
 // differ in ell and s: points prescaled for ell = 1, squared distances times
 // dist_scale[g] = 1/ell_g^2, outputs times scale_out[g].

@@ -8,7 +8,9 @@
 //    float inputs accumulate in float32 for at most 512 rows and are then added
 //    to a float64 accumulator; chunk partials are float64 and are summed in a
 //    fixed order. The SRHT operand is generated from its sign/column
-//    description: X(r, k) = signs[r] (-1)^popcount(r & cols[k]) (times c).
+//    description: X(r, k) = signs[r] (-1)^popcount(r & cols[k]) (times c);
+//    against a row-major real matrix it takes the fast transform instead
+//    (launch_srht_left, sketch.hip) whenever the workspace holds a slab.
 //  * rowmix: out = alpha A + Q W, W d x m float64, one wave per 16 rows x 16
 //    columns, products and sums in float64 with one rounding at the end.
 #include <type_traits>
@@ -422,8 +424,10 @@ static hipError_t launch_reduce_partials(hipStream_t st, const double* partial, 
   return hipGetLastError();
 }
 
+// Rows per partial of the general product: 1024 or more, at most 64 partials
+// (short products still spread over many workgroups).
 static int64_t tn_chunk(int64_t n) {
-  int64_t chunk = 4096;
+  int64_t chunk = 1024;
   while ((n + chunk - 1) / chunk > 64) chunk *= 2;
   return chunk;
 }
@@ -432,7 +436,8 @@ static int64_t tn_chunk(int64_t n) {
 // N <= 16: Z = Q^T A, Q^T y): one workgroup per chunk of rows, every thread
 // owns the columns t, t + 256, ... of X against all N columns of Y, whose row
 // is the same for the whole workgroup (scalar loads). Products of float inputs
-// are exact in float64 and are summed in float64.
+// are exact in float64 (a float64 Y, as in Y'^T u, gives rounded float64
+// products); all sums are float64.
 constexpr int kSkinnyMaxM = 1024;
 constexpr int kSkinnyMaxN = 16;
 static int64_t skinny_chunk(int64_t n) {
@@ -453,10 +458,10 @@ size_t tn_workspace(int64_t n, int M, int N) {
   return bs > b ? bs : b;
 }
 
-template <typename RX, int CPM, int NN>
+template <typename RX, typename RY, int CPM, int NN>
 __global__ __launch_bounds__(256) void gemm_tn_skinny_kernel(int64_t n, int64_t chunk, int M, int N,
                                                              const RX* __restrict__ X, int64_t ldx,
-                                                             const RX* __restrict__ Y, int64_t ldy,
+                                                             const RY* __restrict__ Y, int64_t ldy,
                                                              double* __restrict__ partial) {
   // the Y rows of the current 256-row tile, converted to float64 once (thread
   // t converts row t); every thread then reads each row as a broadcast
@@ -515,27 +520,31 @@ __global__ __launch_bounds__(256) void gemm_tn_skinny_kernel(int64_t n, int64_t 
   }
 }
 
-template <typename RX, int CPM>
+template <typename RX, typename RY, int CPM>
 static hipError_t launch_skinny_cpm(hipStream_t st, int64_t n, int64_t chunk, int64_t nch, int M, int N,
-                                    const RX* X, int64_t ldx, const RX* Y, int64_t ldy, double* partial) {
+                                    const RX* X, int64_t ldx, const RY* Y, int64_t ldy, double* partial) {
   const dim3 g((unsigned)nch), b(256);
   if (N <= 1)
-    hipLaunchKernelGGL((gemm_tn_skinny_kernel<RX, CPM, 1>), g, b, 0, st, n, chunk, M, N, X, ldx, Y, ldy, partial);
+    hipLaunchKernelGGL((gemm_tn_skinny_kernel<RX, RY, CPM, 1>), g, b, 0, st, n, chunk, M, N, X, ldx, Y, ldy,
+                       partial);
   else if (N <= 4)
-    hipLaunchKernelGGL((gemm_tn_skinny_kernel<RX, CPM, 4>), g, b, 0, st, n, chunk, M, N, X, ldx, Y, ldy, partial);
+    hipLaunchKernelGGL((gemm_tn_skinny_kernel<RX, RY, CPM, 4>), g, b, 0, st, n, chunk, M, N, X, ldx, Y, ldy,
+                       partial);
   else if (N <= 8)
-    hipLaunchKernelGGL((gemm_tn_skinny_kernel<RX, CPM, 8>), g, b, 0, st, n, chunk, M, N, X, ldx, Y, ldy, partial);
+    hipLaunchKernelGGL((gemm_tn_skinny_kernel<RX, RY, CPM, 8>), g, b, 0, st, n, chunk, M, N, X, ldx, Y, ldy,
+                       partial);
   else
-    hipLaunchKernelGGL((gemm_tn_skinny_kernel<RX, CPM, 16>), g, b, 0, st, n, chunk, M, N, X, ldx, Y, ldy, partial);
+    hipLaunchKernelGGL((gemm_tn_skinny_kernel<RX, RY, CPM, 16>), g, b, 0, st, n, chunk, M, N, X, ldx, Y, ldy,
+                       partial);
   return hipGetLastError();
 }
 
-template <typename RX>
+template <typename RX, typename RY>
 static hipError_t launch_skinny(hipStream_t st, int64_t n, int64_t chunk, int64_t nch, int M, int N, const RX* X,
-                                int64_t ldx, const RX* Y, int64_t ldy, double* partial) {
-  if (M <= 256) return launch_skinny_cpm<RX, 1>(st, n, chunk, nch, M, N, X, ldx, Y, ldy, partial);
-  if (M <= 512) return launch_skinny_cpm<RX, 2>(st, n, chunk, nch, M, N, X, ldx, Y, ldy, partial);
-  return launch_skinny_cpm<RX, 4>(st, n, chunk, nch, M, N, X, ldx, Y, ldy, partial);
+                                int64_t ldx, const RY* Y, int64_t ldy, double* partial) {
+  if (M <= 256) return launch_skinny_cpm<RX, RY, 1>(st, n, chunk, nch, M, N, X, ldx, Y, ldy, partial);
+  if (M <= 512) return launch_skinny_cpm<RX, RY, 2>(st, n, chunk, nch, M, N, X, ldx, Y, ldy, partial);
+  return launch_skinny_cpm<RX, RY, 4>(st, n, chunk, nch, M, N, X, ldx, Y, ldy, partial);
 }
 
 hipError_t launch_gemm_tn(hipStream_t st, int64_t n, int M, int N, const TnOperand& X, const TnOperand& Y,
@@ -546,6 +555,19 @@ hipError_t launch_gemm_tn(hipStream_t st, int64_t n, int M, int N, const TnOpera
   const int64_t chunk = tn_chunk(n);
   const int64_t nch = (n + chunk - 1) / chunk;
   double* partial = static_cast<double*>(ws);
+  // an SRHT Omega against a row-major real matrix: the fast transform, column
+  // by column, when a slab of at least one transform chunk fits the workspace
+  if (X.kind == 2 && Y.kind == 0 && (Y.dtype == 0 || Y.dtype == 1) && Y.ld == N) {
+    const size_t elem = Y.dtype == 0 ? sizeof(double) : sizeof(float);
+    const int64_t S = srht_left_slab(n, M, N, elem, (size_t)nch * M * N * sizeof(double));
+    if (S > 0) {
+      if (Y.dtype == 0)
+        return launch_srht_left<double>(st, n, M, X.signs, X.cols, static_cast<const double*>(Y.ptr), N, x_scale, out,
+                                        ws, S);
+      return launch_srht_left<float>(st, n, M, X.signs, X.cols, static_cast<const float*>(Y.ptr), N, x_scale, out, ws,
+                                     S);
+    }
+  }
   // fast path: transposed float/bf16 Omega against a row-major float matrix
   const bool y16 = Y.kind == 0 && Y.dtype == 1 && Y.ld % 4 == 0 && reinterpret_cast<uintptr_t>(Y.ptr) % 16 == 0;
   const bool x16 = X.kind == 1 && (X.dtype == 1 || X.dtype == 2) && X.ld % 8 == 0 &&
@@ -564,16 +586,23 @@ hipError_t launch_gemm_tn(hipStream_t st, int64_t n, int M, int N, const TnOpera
                        nch, count, x_scale, out);
     return hipGetLastError();
   }
-  // skinny real x real products (exact float64 products and sums either way)
-  if (X.kind == 0 && Y.kind == 0 && X.dtype == Y.dtype && X.dtype != 2 && M <= kSkinnyMaxM && N <= kSkinnyMaxN &&
-      (f64 || X.dtype == 1)) {
+  // skinny real x real products (float64 sums; products of float inputs are
+  // exact, a float64 operand makes them rounded float64 products)
+  const bool mixed = X.dtype == 1 && Y.dtype == 0;
+  if (X.kind == 0 && Y.kind == 0 && (X.dtype == Y.dtype || mixed) && X.dtype != 2 && M <= kSkinnyMaxM &&
+      N <= kSkinnyMaxN && (f64 || X.dtype == 1)) {
     const int64_t sc = skinny_chunk(n);
     const int64_t ns = (n + sc - 1) / sc;
-    hipError_t e = X.dtype == 0
-                       ? launch_skinny<double>(st, n, sc, ns, M, N, static_cast<const double*>(X.ptr), X.ld,
-                                               static_cast<const double*>(Y.ptr), Y.ld, partial)
-                       : launch_skinny<float>(st, n, sc, ns, M, N, static_cast<const float*>(X.ptr), X.ld,
-                                              static_cast<const float*>(Y.ptr), Y.ld, partial);
+    hipError_t e;
+    if (X.dtype == 0)
+      e = launch_skinny(st, n, sc, ns, M, N, static_cast<const double*>(X.ptr), X.ld,
+                        static_cast<const double*>(Y.ptr), Y.ld, partial);
+    else if (mixed)
+      e = launch_skinny(st, n, sc, ns, M, N, static_cast<const float*>(X.ptr), X.ld, static_cast<const double*>(Y.ptr),
+                        Y.ld, partial);
+    else
+      e = launch_skinny(st, n, sc, ns, M, N, static_cast<const float*>(X.ptr), X.ld, static_cast<const float*>(Y.ptr),
+                        Y.ld, partial);
     if (e != hipSuccess) return e;
     return launch_reduce_partials(st, partial, ns, count, x_scale, out);
   }

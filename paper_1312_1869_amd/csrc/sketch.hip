@@ -479,4 +479,118 @@ template hipError_t launch_sketch_srht<float>(hipStream_t, int, int, const float
 template hipError_t launch_sketch_srht<double>(hipStream_t, int, int, const double*, const int32_t*, int64_t,
                                                int, double, double, double*, double*, int);
 
+
+// ------------------------------------------------------------------ Omega^T M
+//
+// Omega^T M for an SRHT Omega and a real n x N matrix M (F = Omega^T Q and the
+// adjoint's Omega^T Y'): column c of M is transformed like a row of K in the
+// sketch (chunks of 2048, the same butterflies and selections), which costs
+// n (11 + 1) adds per column instead of the 2 n d of a dense product. One
+// wave per column, float64 throughout: the products D_j M[j, c] are exact and
+// every sum is a float64 sum. M arrives in slabs of S rows, transposed (mt: N
+// rows of S entries); the sums go to outT (N x d, one contiguous row per
+// column). pass: 0 = first slab (store), 1 = later slab (add).
+template <typename T, int NQ>
+__global__ __launch_bounds__(256) void srht_left_kernel(const T* __restrict__ mt, int64_t S, int64_t row0, int N,
+                                                        const int8_t* __restrict__ signs,
+                                                        const int32_t* __restrict__ cols, int d, int pass,
+                                                        double* __restrict__ outT) {
+  __shared__ __align__(16) double smem[4 * kBufWords];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * 4 + wave;
+  if (c >= N) return;  // whole waves; the transform synchronises within the wave only
+  double* buf = smem + wave * kBufWords;
+  int pk[NQ];
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int k = lane + 64 * q;
+    pk[q] = (k < d) ? cols[k] : 0;
+    acc[q] = 0.0;
+  }
+  const T* col = mt + (int64_t)c * S;
+  const int64_t nchunks = (S + kChunk - 1) / kChunk;
+  for (int64_t ch = 0; ch < nchunks; ++ch) {
+    const int64_t base = ch * kChunk;
+    double v[kChunkRegs];
+#pragma unroll
+    for (int r = 0; r < kChunkRegs; ++r) {
+      const int64_t j = base + r * 64 + lane;
+      double x = 0.0;
+      if (j < S) {
+        x = (double)col[j];
+        if (signs[row0 + j] < 0) x = -x;
+      }
+      v[r] = x;
+    }
+    // chunk index within the whole of n: row0 is a multiple of the chunk, or 0
+    srht_chunk_accumulate<double, NQ>(v, buf, lane, (row0 + base) / kChunk, pk, d, acc);
+  }
+  double* o = outT + (int64_t)c * d;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int k = lane + 64 * q;
+    if (k < d) o[k] = pass == 0 ? acc[q] : o[k] + acc[q];
+  }
+}
+
+// out[k][c] = scale * outT[c][k] (d x N from N x d) through 32 x 32 LDS tiles.
+__global__ void scale_transpose_kernel(const double* __restrict__ outT, int N, int d, double scale,
+                                       double* __restrict__ out) {
+  __shared__ double tile[32][33];
+  const int c0 = blockIdx.x * 32, k0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int c = c0 + r, k = k0 + tx;
+    tile[r][tx] = (c < N && k < d) ? outT[(int64_t)c * d + k] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int k = k0 + r, c = c0 + tx;
+    if (k < d && c < N) out[(int64_t)k * N + c] = scale * tile[tx][r];
+  }
+}
+
+template <typename T, int NQ>
+static hipError_t launch_srht_left_nq(hipStream_t st, int64_t n, int d, const int8_t* signs, const int32_t* cols,
+                                      const T* M, int N, double scale, double* out, void* ws, int64_t S) {
+  double* outT = static_cast<double*>(ws);
+  T* slab = reinterpret_cast<T*>(static_cast<char*>(ws) + (((size_t)N * d * sizeof(double) + 255) & ~(size_t)255));
+  const dim3 grid((unsigned)((N + 3) / 4));
+  for (int64_t row0 = 0; row0 < n; row0 += S) {
+    hipError_t e = launch_transpose(st, S, N, M + row0 * N, S, slab, sizeof(T) == 8);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((srht_left_kernel<T, NQ>), grid, dim3(256), 0, st, slab, S, row0, N, signs, cols, d,
+                       row0 == 0 ? 0 : 1, outT);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(scale_transpose_kernel, dim3((unsigned)((N + 31) / 32), (unsigned)((d + 31) / 32)), dim3(256),
+                     0, st, outT, N, d, scale, out);
+  return hipGetLastError();
+}
+
+int64_t srht_left_slab(int64_t n, int d, int N, size_t elem, size_t ws_bytes) {
+  const size_t head = ((size_t)N * d * sizeof(double) + 255) & ~(size_t)255;
+  if (d > 16 * 64 || N < 1 || ws_bytes <= head || (n & (n - 1)) != 0) return 0;
+  int64_t S = n;
+  while (S > kChunk && (size_t)S * N * elem > ws_bytes - head) S >>= 1;
+  return (size_t)S * N * elem <= ws_bytes - head ? S : 0;
+}
+
+template <typename T>
+hipError_t launch_srht_left(hipStream_t st, int64_t n, int d, const int8_t* signs, const int32_t* cols, const T* M,
+                            int N, double scale, double* out, void* ws, int64_t S) {
+  const int nq = (d + 63) / 64;
+  if (nq <= 1) return launch_srht_left_nq<T, 1>(st, n, d, signs, cols, M, N, scale, out, ws, S);
+  if (nq <= 2) return launch_srht_left_nq<T, 2>(st, n, d, signs, cols, M, N, scale, out, ws, S);
+  if (nq <= 4) return launch_srht_left_nq<T, 4>(st, n, d, signs, cols, M, N, scale, out, ws, S);
+  if (nq <= 8) return launch_srht_left_nq<T, 8>(st, n, d, signs, cols, M, N, scale, out, ws, S);
+  return launch_srht_left_nq<T, 16>(st, n, d, signs, cols, M, N, scale, out, ws, S);
+}
+template hipError_t launch_srht_left<float>(hipStream_t, int64_t, int, const int8_t*, const int32_t*, const float*,
+                                            int, double, double*, void*, int64_t);
+template hipError_t launch_srht_left<double>(hipStream_t, int64_t, int, const int8_t*, const int32_t*, const double*,
+                                             int, double, double*, void*, int64_t);
+
 }  // namespace lr
