@@ -275,6 +275,50 @@ def test_omega_t_q_product_against_oracle(prec):
     assert err <= 520 * 2.0 ** -24
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_srht_omega_t_q_transform_against_oracle(prec):
+    """F = Omega^T Q for an SRHT Omega (Def. 1), read back from the LU factors
+    as above. n = 16384 with d = 100 (not a multiple of the 64 outputs a lane
+    group owns): in float32 the product takes the column-wise fast transform
+    over eight 2048-row slabs, in float64 the workspace holds no slab and the
+    generated-operand product runs instead. Both sum exact products in float64
+    (transform depth log2(2048) plus the chunk and slab sums), so the bar is
+    64 u64 relative to sum_r |Omega_ri| |Q_rj| = c sum_r |Q_rj|."""
+    dev = device()
+    a = api()
+    n, d, m = 16384, 100, 3
+    rng = np.random.default_rng(37)
+    q = np.linalg.qr(rng.standard_normal((n, d)))[0]
+    q = q.astype(np.float32).astype(np.float64)
+    r = np.triu(rng.standard_normal((d, d)), 1) + np.diag(1.0 + np.abs(rng.standard_normal(d)))
+    w = W.small(W.WORKLOADS["C2"], n, d=d, m=m)
+    om_np, om = omega_pair(w, prec, dev)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    A = rng.standard_normal((n, m))
+    note(f"SRHT Omega^T Q product n={n} d={d} prec={prec}")
+    sol = a.lowrank_solve(to_dev(q, dt, dev), to_dev(r, torch.float64, dev), om, prec, w.sigma2, to_dev(A, dt, dev))
+    torch.cuda.synchronize()
+    assert int(sol.info.item()) >= 0
+    flu = sol.Flu.cpu().numpy()
+    piv = sol.piv.cpu().numpy()
+    lo, up = np.tril(flu, -1) + np.eye(d), np.triu(flu)
+    f, lu_abs = lo @ up, np.abs(lo) @ np.abs(up)
+    for k in range(d - 1, -1, -1):
+        p = int(piv[k])
+        f[[k, p]] = f[[p, k]]
+        lu_abs[[k, p]] = lu_abs[[p, k]]
+    ref = osk.omega_t_apply(om_np, q)
+    scale = np.abs(q).sum(axis=0)[None, :] / np.sqrt(n)
+    # product bar plus the float64 LU's backward error and the reconstruction
+    # product (gamma_d |L||U| each)
+    u = 2.0 ** -53
+    bar = 64 * u * scale + 2 * (d + 2) * u * lu_abs
+    err = float((np.abs(f - ref) / bar).max())
+    note(f"  max |F - Omega^T Q| / bar = {err:.3e}; max error relative to |Omega|^T |Q|: "
+         f"{float((np.abs(f - ref) / scale).max()):.3e}")
+    assert err <= 1.0
+
+
 def test_c2_full_fp32_against_fp64_path():
     """The FP32-vs-FP64 workload at full size (n = 65536, D = 3, SE, SRHT
     d = 256, A 65536 x 8). The FP64 path is pinned to the oracle: sketch rows
