@@ -26,6 +26,27 @@ namespace lr {
 constexpr int kUpdThreads = 256;
 constexpr int kUpdCols = 64;
 
+// Column block and matrix of this workgroup for the update kernels (grid:
+// column blocks x matrices). Workgroups go to the 8 XCDs round robin by their
+// linear id, so the launch order would spread the column blocks of one matrix
+// over every XCD and fetch its reflector panel V into every L2. Here each
+// XCD takes whole matrices: its k-th workgroup is column block k mod nx of
+// matrix xcd + 8 (k / nx). A bijection when the matrix count is a multiple of
+// 8; otherwise the launch order is kept.
+constexpr int kXcds = 8;
+__device__ __forceinline__ void xcd_block(int& cbx, int& b) {
+  const int nx = (int)gridDim.x, ny = (int)gridDim.y;
+  if (ny % kXcds != 0) {
+    cbx = (int)blockIdx.x;
+    b = (int)blockIdx.y;
+    return;
+  }
+  const int lin = (int)blockIdx.x + nx * (int)blockIdx.y;
+  const int k = lin / kXcds;
+  cbx = k % nx;
+  b = lin % kXcds + kXcds * (k / nx);
+}
+
 // Sum of NV values (NV a power of two <= 16) over the TPB-thread block; every
 // thread gets the totals. Inside each 16-lane row a transpose reduction halves
 // the vector at every DPP exchange (partners: half-row mirror, xor 8, xor 2,
@@ -330,7 +351,8 @@ __global__ __launch_bounds__(kUpdThreads) void panel_apply_kernel(const T* Vmat,
   __shared__ T wsh[NB][UC];
   __shared__ T Ts[NB * NB];
 
-  const int b = blockIdx.y;
+  int cbx, b;
+  xcd_block(cbx, b);
   const int m = (b == nbatch - 1) ? m_last : m_full;
   const T* V = Vmat + (int64_t)b * vstride;
   T* B = Bmat + (int64_t)b * bstride;
@@ -341,7 +363,7 @@ __global__ __launch_bounds__(kUpdThreads) void panel_apply_kernel(const T* Vmat,
   const int lane = t & 63;
   const int tc = t % TPR;
   const int rg = t / TPR;
-  const int cbase = col_begin + blockIdx.x * UC;
+  const int cbase = col_begin + cbx * UC;
   const int col0 = cbase + tc * CPT;
   // vector access needs every column of the vector present and 16-byte alignment
   const bool vec_ok = (col0 + CPT <= col_end) && (((int64_t)ld * sizeof(T)) % 16 == 0) && (col0 % CPT == 0);
@@ -527,7 +549,8 @@ __global__ __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(1, 
   __shared__ T Ws[kOuter][kOuter + 1];
   __shared__ T Ts[kOuter][kOuter + 1];
 
-  const int b = blockIdx.y;
+  int cbx, b;
+  xcd_block(cbx, b);
   const int m = (b == nbatch - 1) ? m_last : m_full;
   const T* V = Vmat + (int64_t)b * vstride;
   T* B = Bmat + (int64_t)b * bstride;
@@ -538,7 +561,7 @@ __global__ __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(1, 
   const int lane = t & 63;
   const int l15 = lane & 15;
   const int lg = lane >> 4;
-  const int cb0 = (MODE == 2) ? P0 : col_begin + blockIdx.x * kOuter;
+  const int cb0 = (MODE == 2) ? P0 : col_begin + cbx * kOuter;
   const int cend = (MODE == 2) ? P0 + W : col_end;
   const bool vec_ld = ((int64_t)ld * sizeof(T)) % 16 == 0;
   const bool vec_v = vec_ld && (reinterpret_cast<uintptr_t>(V) % 16 == 0) && (P0 % 4 == 0);
