@@ -22,6 +22,29 @@ namespace lr {
 
 constexpr int kTnFlushSteps = 16;  // 16 steps of 32 rows
 
+// Output tile (bx, by) and row chunk bz of a transposed-product workgroup
+// (grid: M tiles x N tiles x row chunks). Workgroups go to the 8 XCDs round
+// robin by linear id, so in launch order the tiles of one row chunk would
+// read its rows of X and Y into every L2. Here each XCD takes whole row
+// chunks: its k-th workgroup is tile k mod (nx ny) of chunk xcd + 8 k / (nx ny).
+// A bijection when the chunk count is a multiple of 8; otherwise the launch
+// order is kept.
+__device__ __forceinline__ void xcd_tile(int& bx, int& by, int& bz) {
+  const int nx = (int)gridDim.x, ny = (int)gridDim.y, nz = (int)gridDim.z;
+  if (nz % 8 != 0) {
+    bx = (int)blockIdx.x;
+    by = (int)blockIdx.y;
+    bz = (int)blockIdx.z;
+    return;
+  }
+  const int64_t lin = (int64_t)blockIdx.x + (int64_t)nx * ((int64_t)blockIdx.y + (int64_t)ny * blockIdx.z);
+  const int64_t k = lin / 8;
+  const int64_t t = k % ((int64_t)nx * ny);
+  bz = (int)(lin % 8 + 8 * (k / ((int64_t)nx * ny)));
+  bx = (int)(t % nx);
+  by = (int)(t / nx);
+}
+
 template <typename R>
 struct Frag8 {
   R v[8];
@@ -92,9 +115,11 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(int64_t n, int64_t chunk, 
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int fl = lane & 15, fg = lane >> 4;
-  const int i0 = blockIdx.x * 64 + (w & 1) * 32;
-  const int j0 = blockIdx.y * 64 + (w >> 1) * 32;
-  const int64_t rbeg = (int64_t)blockIdx.z * chunk;
+  int bx, by, bz;
+  xcd_tile(bx, by, bz);
+  const int i0 = bx * 64 + (w & 1) * 32;
+  const int j0 = by * 64 + (w >> 1) * 32;
+  const int64_t rbeg = (int64_t)bz * chunk;
   int64_t rend = rbeg + chunk;
   if (rend > n) rend = n;
 
@@ -144,7 +169,7 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(int64_t n, int64_t chunk, 
       }
     }
   }
-  double* out = partial + (int64_t)blockIdx.z * M * N;
+  double* out = partial + (int64_t)bz * M * N;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -173,9 +198,11 @@ __global__ __launch_bounds__(256) void gemm_tn_xt_kernel(int64_t n, int64_t chun
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int fl = lane & 15, fg = lane >> 4;
-  const int i0 = blockIdx.x * 64 + (w & 1) * 32;
-  const int j0 = blockIdx.y * 128 + (w >> 1) * 64;
-  const int64_t rbeg = (int64_t)blockIdx.z * chunk;
+  int bx, by, bz;
+  xcd_tile(bx, by, bz);
+  const int i0 = bx * 64 + (w & 1) * 32;
+  const int j0 = by * 128 + (w >> 1) * 64;
+  const int64_t rbeg = (int64_t)bz * chunk;
   int64_t rend = rbeg + chunk;
   if (rend > n) rend = n;
 
@@ -323,7 +350,7 @@ __global__ __launch_bounds__(256) void gemm_tn_xt_kernel(int64_t n, int64_t chun
     mma_step(s2);
   }
   flush();
-  double* out = partial + (int64_t)blockIdx.z * M * N;
+  double* out = partial + (int64_t)bz * M * N;
 #pragma unroll
   for (int f = 0; f < 2; ++f)
 #pragma unroll
