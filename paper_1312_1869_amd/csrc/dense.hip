@@ -8,7 +8,8 @@
 //    right-hand-side columns, keeps them whole in LDS (d x kTrNc doubles) and
 //    sweeps the triangle in blocks of 64 rows: the rows of a block first take
 //    the contribution of every solved block (factor tiles staged through LDS,
-//    two outputs per thread), then one wave per two columns finishes the
+//    the next tile requested while the current one is used, two outputs per
+//    thread), then one wave per two columns finishes the
 //    64 x 64 diagonal triangle with the row held by its lane and the solved
 //    entries broadcast lane to lane. Modes:
 //      LU:       X <- U^{-1} L^{-1} P X for the getrf factors of F (row
@@ -127,6 +128,7 @@ constexpr int kTrNc = 8;     // right-hand-side columns per workgroup
 constexpr int kTrBlk = 64;   // rows per block
 constexpr int kTrQ = 32;     // factor columns staged per update step
 constexpr int kTrMaxD = 1024;
+static_assert(kTrQ <= kTrBlk && (kTrQ * kTrBlk) % 256 == 0, "factor tiles fit the 64 x 65 LDS tile");
 
 // Factor entry of the triangle being applied (row r, column q of the triangle).
 //   LU lower:  F[r][q] (unit diagonal)    LU upper:  F[r][q]
@@ -154,21 +156,40 @@ __device__ void trsm_sweep(const double* __restrict__ Fm, int d, double* xs, dou
     const int qbeg = UPPER ? r0 + nb : 0;
     const int qend = UPPER ? d : r0;
     double s0 = 0.0, s1 = 0.0;
+    // the factor tile of step q0 + kTrQ is requested into registers before
+    // the products of step q0, so its load latency overlaps them
+    constexpr int kPer = kTrQ * kTrBlk / 256;
+    auto fetch = [&](int q0, double (&dst)[kPer]) {
+      const int nq = min(kTrQ, qend - q0);
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int e = t + 256 * u;
+        int q, r;
+        if (CHOL && UPPER) {  // contiguous along r
+          r = e % kTrBlk;
+          q = e / kTrBlk;
+        } else {              // contiguous along q
+          q = e % kTrQ;
+          r = e / kTrQ;
+        }
+        dst[u] = (q < nq && r < nb) ? tri_at<CHOL, UPPER>(Fm, d, r0 + r, q0 + q) : 0.0;
+      }
+    };
+    double pre[kPer];
+    if (qbeg < qend) fetch(qbeg, pre);
     for (int q0 = qbeg; q0 < qend; q0 += kTrQ) {
       const int nq = min(kTrQ, qend - q0);
       // tile[q][r] = T(r0 + r, q0 + q)
-      for (int e = t; e < kTrQ * kTrBlk; e += 256) {
-        int q, r;
-        if (CHOL && UPPER) {  // contiguous along r
-          r = e & 63;
-          q = e >> 6;
-        } else {              // contiguous along q
-          q = e & 31;
-          r = e >> 5;
-        }
-        tile[q][r] = (q < nq && r < nb) ? tri_at<CHOL, UPPER>(Fm, d, r0 + r, q0 + q) : 0.0;
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int e = t + 256 * u;
+        if (CHOL && UPPER)
+          tile[e / kTrBlk][e % kTrBlk] = pre[u];
+        else
+          tile[e % kTrQ][e / kTrQ] = pre[u];
       }
       __syncthreads();
+      if (q0 + kTrQ < qend) fetch(q0 + kTrQ, pre);
       for (int q = 0; q < nq; ++q) {
         const double xq = xs[(q0 + q) * kTrNc + uc];
         s0 = fma(tile[q][ur], xq, s0);
