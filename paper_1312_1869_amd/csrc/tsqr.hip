@@ -246,19 +246,17 @@ __global__ __launch_bounds__(TPB) void panel_factor_kernel(T* __restrict__ A, in
       if (lr == c) a[k][c] = beta;
     }
     // w[c'] = v^T x_{c'} for c' > c ; y[c1] = v_{c1}^T v for c1 < c
+    // (i > c: a[k][i] is x_i(lr); i < c: a[k][i] is the stored reflector entry
+    // v_i(lr) for lr > i, so both sums are v^T a[:, i]). Rows above c and
+    // rows past the panel have vk = 0 and add exact zeros, so no row mask.
     T wv[NB];
 #pragma unroll
     for (int i = 0; i < NB; ++i) wv[i] = 0;
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
-      const int lr = t + k * TPB;
-      if (lr < rows && lr >= c) {
-        // i > c: a[k][i] is x_i(lr); i < c: a[k][i] is the stored reflector
-        // entry v_i(lr) (lr >= c > i), so both sums are v^T a[:, i].
 #pragma unroll
-        for (int i = 0; i < NB; ++i)
-          if (i != c) wv[i] += vk[k] * a[k][i];
-      }
+      for (int i = 0; i < NB; ++i)
+        if (i != c) wv[i] += vk[k] * a[k][i];
     }
     block_sum_vec<T, NB, TPB>(wv, nbw, red, res);
     if (t == 0) {
@@ -267,11 +265,13 @@ __global__ __launch_bounds__(TPB) void panel_factor_kernel(T* __restrict__ A, in
       for (int i = 0; i < NB; ++i)
         if (i < c) s_y[c * NB + i] = wv[i];
     }
+    // columns past nbw are zero with wv = 0 there, rows above c have vk = 0:
+    // both updates subtract exact zeros, so neither is masked
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
 #pragma unroll
       for (int i = 0; i < NB; ++i)
-        if (i > c && i < nbw) a[k][i] -= tau * wv[i] * vk[k];
+        if (i > c) a[k][i] -= tau * wv[i] * vk[k];
     }
   });
   __syncthreads();
