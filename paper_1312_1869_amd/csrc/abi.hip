@@ -247,7 +247,7 @@ struct BackWs {
   size_t off_yp, off_sk, off_tn, off_za, off_wa, off_xa, off_zb, off_wb, off_xb, off_u64, off_b64, off_e, off_p,
       off_phi, off_sinv, off_t, off_g2, off_h, off_u, off_eu, off_ca, off_aa, off_xy, off_by, off_xbm, off_u1, off_u2,
       off_eu1, off_eu2, off_cqb, off_oo, off_v1, off_pta, off_oa, off_fa, off_oou, off_m1, off_m2, off_z1, off_z2,
-      off_ox, off_ob, off_fqx, off_fqb, off_oou2, total;
+      off_ox, off_ob, off_fqx, off_fqb, off_oou2, off_tdm, total;
 };
 
 BackWs back_layout(int64_t n, int32_t D, int32_t d, int32_t m, int32_t prec) {
@@ -307,6 +307,7 @@ BackWs back_layout(int64_t n, int32_t D, int32_t d, int32_t m, int32_t prec) {
   take(w.off_fqx, dm8);
   take(w.off_fqb, dm8);
   take(w.off_oou2, dm8);
+  take(w.off_tdm, dm8);
   w.total = off;
   return w;
 }
@@ -823,8 +824,18 @@ lr_status lr_backward(void* stream, int64_t n, int32_t D, const float* X, const 
     LR_HIP(launch_rowmix_f64out(st, n, d, m, Q, xb, inv_s2, V, b64, prec == LR_PREC_F64));
     if (dA != nullptr) LR_HIP(launch_rowmix_info(st, n, d, m, Q, xb, inv_s2, V, dA, prec == LR_PREC_F64, nullptr));
     const TnOperand bo = f64_operand(b64, m);
-    LR_HIP(launch_gemm_tn(st, n, m, d, uo, ypo, 1.0, XY, tn, true));
-    LR_HIP(launch_gemm_tn(st, n, m, d, bo, ypo, 1.0, BY, tn, true));
+    // X^T Y' and B^T Y' (m x d): for m <= 16 as Y'^T X (d x m) on the skinny
+    // product, then transposed
+    if (m <= 16) {
+      double* tdm = dptr(w.off_tdm);
+      LR_HIP(launch_gemm_tn(st, n, d, m, ypo, uo, 1.0, tdm, tn, true));
+      LR_HIP(launch_transpose(st, d, m, tdm, d, XY, true));
+      LR_HIP(launch_gemm_tn(st, n, d, m, ypo, bo, 1.0, tdm, tn, true));
+      LR_HIP(launch_transpose(st, d, m, tdm, d, BY, true));
+    } else {
+      LR_HIP(launch_gemm_tn(st, n, m, d, uo, ypo, 1.0, XY, tn, true));
+      LR_HIP(launch_gemm_tn(st, n, m, d, bo, ypo, 1.0, BY, tn, true));
+    }
     LR_HIP(launch_gemm_tn(st, n, m, m, uo, bo, 1.0, XB, tn, true));
     LR_HIP(launch_gemm_dd(st, d, m, d, 1.0, Phi, d, true, wa, m, false, 0.0, U1, m));
     LR_HIP(launch_gemm_dd(st, d, m, d, 1.0, Phi, d, true, wb, m, false, 0.0, U2, m));
