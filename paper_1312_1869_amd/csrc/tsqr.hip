@@ -25,6 +25,7 @@ namespace lr {
 
 constexpr int kUpdThreads = 256;
 constexpr int kUpdCols = 64;
+constexpr int kNarrowCols = 8;  // float columns per workgroup of a narrow update over few matrices
 
 // Column block and matrix of this workgroup for the update kernels (grid:
 // column blocks x matrices). Workgroups go to the 8 XCDs round robin by their
@@ -1012,12 +1013,25 @@ static hipError_t launch_panel_factor_nb(hipStream_t st, int rpt, T* A, int64_t 
 }
 
 // Narrow updates (at most 64 columns, the inner panels inside an outer panel)
-// take 16-column workgroups, so a batch of a few matrices still fills the chip.
+// take 16-column workgroups, so a batch of a few matrices still fills the chip;
+// float updates that would get at most one 16-column workgroup per CU take
+// 8-column ones (C3 leaves: TSQR 27.7 -> 27.0 ms; 4 columns measured 27.6).
 template <typename T, int NB, bool TRANS>
 static hipError_t launch_apply_nb(hipStream_t st, const T* V, int64_t vstride, T* B, int64_t bstride,
                                   const QrShape& s, int p0, int nbw, int c0, int c1, const T* tm) {
   if (c1 <= c0) return hipSuccess;
   const int64_t tbs = (int64_t)s.npanels * NB * NB;
+  if constexpr (sizeof(T) == 4 && TRANS) {
+    if (c1 - c0 <= 64 && s.nbatch * ((c1 - c0 + 15) / 16) <= 256) {
+      // few workgroups at 16 columns (one per CU or fewer): narrower
+      // workgroups put more row streams in flight
+      const int ncb = (c1 - c0 + kNarrowCols - 1) / kNarrowCols;
+      hipLaunchKernelGGL((panel_apply_kernel<T, NB, TRANS, kNarrowCols>), dim3(ncb, s.nbatch), dim3(kUpdThreads), 0,
+                         st, V, vstride, B, bstride, s.m_full, s.m_last, s.nbatch, s.d, p0, nbw, s.tree_d, c0, c1, tm,
+                         tbs);
+      return hipGetLastError();
+    }
+  }
   if (c1 - c0 <= 64) {
     const int ncb = (c1 - c0 + 15) / 16;
     hipLaunchKernelGGL((panel_apply_kernel<T, NB, TRANS, 16>), dim3(ncb, s.nbatch), dim3(kUpdThreads), 0, st, V,
