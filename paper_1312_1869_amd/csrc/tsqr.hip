@@ -498,6 +498,13 @@ __global__ __launch_bounds__(kUpdThreads) void panel_apply_kernel(const T* Vmat,
 // 64 columns of B of one matrix; its 4 waves split the rows.
 constexpr int kOuter = 64;
 constexpr int kBlkThreads = 256;
+// The Gram matrix V^T V of an outer panel of a few tall blocks is summed by
+// up to kGramSplits workgroups per block over row ranges (partials added in
+// order by block_t_kernel); one workgroup per block would leave most CUs idle.
+constexpr int kGramSplits = 4;
+__host__ __device__ inline int gram_splits(int nbatch, int tree_d) {
+  return (tree_d == 0 && nbatch <= 64) ? kGramSplits : 1;
+}
 
 template <typename T>
 struct BlkMfma;
@@ -638,15 +645,29 @@ __global__ __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(1, 
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[a][c] = M::step(va[a], vb[c], acc[a][c]);
   };
+  // Gram mode over split row ranges: workgroup cbx of gridDim.x takes the
+  // head rows (if first), its share of the interior in 64-row units, and the
+  // tail (if last); a panel off the fast path is done by the first alone
+  const int nsplit = (MODE == 2) ? (int)gridDim.x : 1;
+  const int split = (MODE == 2) ? cbx : 0;
   int r0 = 4 * w;
   const int head_end = fast ? kOuter : nact;
-  for (; r0 < head_end && r0 < nact; r0 += 16) quad_masked(r0);
+  if (split == 0)
+    for (; r0 < head_end && r0 < nact; r0 += 16) quad_masked(r0);
   if (fast) {
+    int ihi = nint;
+    if (nsplit > 1) {
+      const int units = (nint - kOuter + 63) / 64;
+      const int per = (units + nsplit - 1) / nsplit;
+      const int ilo = kOuter + min(split * per * 64, nint - kOuter);
+      ihi = kOuter + min((split + 1) * per * 64, nint - kOuter);
+      r0 = ilo + 4 * w;
+    }
     // four row quads per trip; the next trip's loads are issued before this
     // trip's products (two register sets, trips in pairs). Rows of a trip past
     // the interior are clamped to the last interior quad and multiply nothing.
-    // trip k reads rows r0 + 64 k .. r0 + 64 k + 51, all below nint
-    const int ntrip = (nint - r0 >= 52) ? (nint - r0 - 52) / 64 + 1 : 0;
+    // trip k reads rows r0 + 64 k .. r0 + 64 k + 51, all below ihi
+    const int ntrip = (ihi - r0 >= 52) ? (ihi - r0 - 52) / 64 + 1 : 0;
     auto load_trip = [&](int k, T (&va)[4][4], T (&vb)[4][4]) {
       const int rb = r0 + 64 * (k < ntrip ? k : ntrip - 1);
 #pragma unroll
@@ -676,7 +697,9 @@ __global__ __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(1, 
       if (k < ntrip) mma_trip(va0, vb0);
       r0 += 64 * ntrip;
     }
-    for (; r0 < nact; r0 += 16) quad_masked(r0);
+    for (; r0 < ihi; r0 += 16) quad_masked(r0);
+    if (split == nsplit - 1)
+      for (; r0 < nact; r0 += 16) quad_masked(r0);
   }
   // combine the 4 waves' partial sums in LDS, one wave after the other
   for (int ww = 0; ww < 4; ++ww) {
@@ -695,7 +718,7 @@ __global__ __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(1, 
     __syncthreads();
   }
   if (MODE == 2) {
-    T* g = gout + (int64_t)b * kOuter * kOuter;
+    T* g = gout + ((int64_t)split * nbatch + b) * kOuter * kOuter;
     for (int e = t; e < kOuter * kOuter; e += kBlkThreads) g[e] = Ws[e / kOuter][e % kOuter];
     return;
   }
@@ -847,16 +870,17 @@ __global__ __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(1, 
 template <typename T>
 __global__ __launch_bounds__(kBlkThreads) void block_t_kernel(const T* __restrict__ tm, int64_t t_bstride, int nb,
                                                               int P0, int W, const T* __restrict__ gram,
-                                                              T* __restrict__ tbig) {
+                                                              int nsplit, int nbatch, T* __restrict__ tbig) {
   __shared__ T Tb[kOuter][kOuter + 1];
   __shared__ T G[kOuter][kOuter + 1];
   __shared__ T X[kOuter][kOuter + 1];
   const int b = blockIdx.x;
   const int t = threadIdx.x;
-  const T* g = gram + (int64_t)b * kOuter * kOuter;
   for (int e = t; e < kOuter * kOuter; e += kBlkThreads) {
     const int i = e / kOuter, j = e % kOuter;
-    G[i][j] = g[e];
+    T gs = gram[(int64_t)b * kOuter * kOuter + e];
+    for (int q = 1; q < nsplit; ++q) gs += gram[((int64_t)q * nbatch + b) * kOuter * kOuter + e];
+    G[i][j] = gs;
     T v = 0;
     if (i < W && j < W && i / nb == j / nb && i <= j) {
       const int k = i / nb;
@@ -1061,7 +1085,7 @@ static hipError_t launch_apply(hipStream_t st, int nb, const T* V, int64_t vstri
 template <typename T, int MODE>
 static hipError_t launch_block_apply(hipStream_t st, const T* V, int64_t vstride, T* B, int64_t bstride,
                                      const QrShape& s, int P0, int W, int c0, int c1, const T* tbig, T* gout) {
-  const int ncb = (MODE == 2) ? 1 : (c1 - c0 + kOuter - 1) / kOuter;
+  const int ncb = (MODE == 2) ? gram_splits(s.nbatch, s.tree_d) : (c1 - c0 + kOuter - 1) / kOuter;
   if (ncb <= 0) return hipSuccess;
   hipLaunchKernelGGL((block_apply_kernel<T, MODE>), dim3(ncb, s.nbatch), dim3(kBlkThreads), 0, st, V, vstride, B,
                      bstride, s.m_full, s.m_last, s.nbatch, s.d, P0, W, s.tree_d, c0, c1, tbig, gout);
@@ -1098,7 +1122,7 @@ static hipError_t batched_qr(hipStream_t st, T* A, int64_t bstride, const QrShap
     T* tb = tbig + (int64_t)o * s.nbatch * kOuter * kOuter;
     LR_TRY((launch_block_apply<T, 2>(st, A, bstride, A, bstride, s, P0, W, 0, 0, nullptr, gram)));
     hipLaunchKernelGGL(block_t_kernel<T>, dim3(s.nbatch), dim3(kBlkThreads), 0, st, tm, t_bstride, s.nb, P0, W, gram,
-                       tb);
+                       gram_splits(s.nbatch, s.tree_d), s.nbatch, tb);
     LR_TRY(hipGetLastError());
     LR_TRY((launch_block_apply<T, 0>(st, A, bstride, A, bstride, s, P0, W, P0 + W, s.d, tb, nullptr)));
   }
@@ -1248,7 +1272,7 @@ static TsqrPlan make_plan(int64_t n, int d, int leaf_rows) {
   p.off_tbig = off;
   off = align256(off + (size_t)n_outer(d) * p.nleaf * blk * sizeof(T));
   p.off_gram = off;
-  off = align256(off + (size_t)p.nleaf * blk * sizeof(T));
+  off = align256(off + (size_t)kGramSplits * p.nleaf * blk * sizeof(T));
   p.tree = make_tree_plan(p.nleaf, d, off);
   p.total = p.tree.end;
   return p;
@@ -1369,7 +1393,7 @@ static DominoPlan make_domino_plan(int64_t n, int d, int L, int g) {
   p.off_t = off;
   off = align256(off + (size_t)p.groups * tsz * sizeof(T));
   p.off_gram = off;
-  off = align256(off + (size_t)p.groups * blk * sizeof(T));
+  off = align256(off + (size_t)kGramSplits * p.groups * blk * sizeof(T));
   p.off_tbig0 = off;
   off = align256(off + tbig_bytes);
   for (int t = 1; t < g; ++t) {
