@@ -502,6 +502,7 @@ constexpr int kBlkThreads = 256;
 // up to kGramSplits workgroups per block over row ranges (partials added in
 // order by block_t_kernel); one workgroup per block would leave most CUs idle.
 constexpr int kGramSplits = 4;
+constexpr int kRowSplits = 4;  // row shares of a narrow trailing update
 __host__ __device__ inline int gram_splits(int nbatch, int tree_d) {
   return (tree_d == 0 && nbatch <= 64) ? kGramSplits : 1;
 }
@@ -546,12 +547,16 @@ __device__ __forceinline__ void load4(const T* src, int c0, int cend, bool vec, 
 // MODE 2: gout = V^T V             (Gram matrix of the outer panel)
 // V = columns [P0, P0 + W) of Vmat with unit diagonal and zeros above, over the
 // rows of the outer panel's row map; B columns [col_begin, col_end).
+// MODE 0/1 over row shares (phase 1 and 2, rsplit shares per column block,
+// gridDim.x = column blocks x rsplit): phase 1 writes the share's partial
+// V^T B to wpart, phase 2 applies the summed W to the share's rows.
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) void block_apply_kernel(const T* Vmat, int64_t vstride, T* Bmat,
                                                                   int64_t bstride, int m_full, int m_last,
                                                                   int nbatch, int ld, int P0, int W, int tree_d,
                                                                   int col_begin, int col_end,
-                                                                  const T* __restrict__ tbig, T* __restrict__ gout) {
+                                                                  const T* __restrict__ tbig, T* __restrict__ gout,
+                                                                  int phase, int rsplit, T* __restrict__ wpart) {
   using M = BlkMfma<T>;
   using Acc = typename M::Acc;
   __shared__ T Ws[kOuter][kOuter + 1];
@@ -569,7 +574,10 @@ __global__ __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(1, 
   const int lane = t & 63;
   const int l15 = lane & 15;
   const int lg = lane >> 4;
-  const int cb0 = (MODE == 2) ? P0 : col_begin + cbx * kOuter;
+  const bool shared_rows = MODE != 2 && phase != 0;
+  const int ncb_real = shared_rows ? (int)gridDim.x / rsplit : (int)gridDim.x;
+  const int cbk = shared_rows ? cbx % ncb_real : cbx;
+  const int cb0 = (MODE == 2) ? P0 : col_begin + cbk * kOuter;
   const int cend = (MODE == 2) ? P0 + W : col_end;
   const bool vec_ld = ((int64_t)ld * sizeof(T)) % 16 == 0;
   const bool vec_v = vec_ld && (reinterpret_cast<uintptr_t>(V) % 16 == 0) && (P0 % 4 == 0);
@@ -619,6 +627,29 @@ __global__ __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(1, 
     }
   };
 
+  // Row shares (Gram mode, or phase 1/2): share split of nsplit takes the
+  // head rows (if first), interior rows [ilo, ihi) in 64-row units, and the
+  // tail (if last); a panel off the fast path is done by the first alone.
+  const int nsplit = (MODE == 2) ? (int)gridDim.x : (shared_rows ? rsplit : 1);
+  const int split = (MODE == 2) ? cbx : (shared_rows ? cbx / ncb_real : 0);
+  int ilo = kOuter, ihi = nint;
+  if (nsplit > 1) {
+    const int span = nint > kOuter ? nint - kOuter : 0;
+    const int per = ((span + 63) / 64 + nsplit - 1) / nsplit;
+    ilo = kOuter + min(split * per * 64, span);
+    ihi = kOuter + min((split + 1) * per * 64, span);
+  }
+  T* wshare = shared_rows ? wpart + (((int64_t)split * ncb_real + cbk) * nbatch + b) * kOuter * kOuter : nullptr;
+
+  if (MODE != 2 && phase == 2) {
+    // the summed W of every share of this column block
+    for (int e = t; e < kOuter * kOuter; e += kBlkThreads) {
+      T sum = 0;
+      for (int q = 0; q < nsplit; ++q) sum += wpart[(((int64_t)q * ncb_real + cbk) * nbatch + b) * kOuter * kOuter + e];
+      Ws[e / kOuter][e % kOuter] = sum;
+    }
+    __syncthreads();
+  } else {
   // ---- pass 1: W = V^T B (tile (ti, tj) entry (r, c) is W[4r + ti][4c + tj])
   Acc acc[4][4];
 #pragma unroll
@@ -645,24 +676,12 @@ __global__ __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(1, 
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[a][c] = M::step(va[a], vb[c], acc[a][c]);
   };
-  // Gram mode over split row ranges: workgroup cbx of gridDim.x takes the
-  // head rows (if first), its share of the interior in 64-row units, and the
-  // tail (if last); a panel off the fast path is done by the first alone
-  const int nsplit = (MODE == 2) ? (int)gridDim.x : 1;
-  const int split = (MODE == 2) ? cbx : 0;
   int r0 = 4 * w;
   const int head_end = fast ? kOuter : nact;
   if (split == 0)
     for (; r0 < head_end && r0 < nact; r0 += 16) quad_masked(r0);
   if (fast) {
-    int ihi = nint;
-    if (nsplit > 1) {
-      const int units = (nint - kOuter + 63) / 64;
-      const int per = (units + nsplit - 1) / nsplit;
-      const int ilo = kOuter + min(split * per * 64, nint - kOuter);
-      ihi = kOuter + min((split + 1) * per * 64, nint - kOuter);
-      r0 = ilo + 4 * w;
-    }
+    if (nsplit > 1) r0 = ilo + 4 * w;
     // four row quads per trip; the next trip's loads are issued before this
     // trip's products (two register sets, trips in pairs). Rows of a trip past
     // the interior are clamped to the last interior quad and multiply nothing.
@@ -722,6 +741,11 @@ __global__ __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(1, 
     for (int e = t; e < kOuter * kOuter; e += kBlkThreads) g[e] = Ws[e / kOuter][e % kOuter];
     return;
   }
+  if (phase == 1) {
+    for (int e = t; e < kOuter * kOuter; e += kBlkThreads) wshare[e] = Ws[e / kOuter][e % kOuter];
+    return;
+  }
+  }  // pass 1
 
   // ---- W' = T' W (T' = T^T for MODE 0, T for MODE 1); T is upper triangular
   const T* tb = tbig + (int64_t)b * kOuter * kOuter;
@@ -808,12 +832,14 @@ __global__ __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(1, 
     }
   };
   int c0 = 16 * w;
-  for (; c0 < (fast ? kOuter : nact) && c0 < nact; c0 += 64) chunk(c0, std::false_type{});
+  if (split == 0)
+    for (; c0 < (fast ? kOuter : nact) && c0 < nact; c0 += 64) chunk(c0, std::false_type{});
   if (fast) {
+    if (nsplit > 1) c0 = ilo + 16 * w;
     // interior chunks: the next chunk's V rows and B entries are loaded before
     // this chunk's products (two register sets, chunks in pairs; the load past
     // the last chunk re-reads it and is unused)
-    const int nch = (nint - c0 >= 16) ? (nint - c0 - 16) / 64 + 1 : 0;
+    const int nch = (ihi - c0 >= 16) ? (ihi - c0 - 16) / 64 + 1 : 0;
     auto load_chunk = [&](int k, T (&va)[4][4], T (&bo)[4][4]) {
       const int cc = c0 + 64 * (k < nch ? k : nch - 1);
 #pragma unroll
@@ -858,7 +884,9 @@ __global__ __launch_bounds__(kBlkThreads) __attribute__((amdgpu_waves_per_eu(1, 
       if (k < nch) run_chunk(k, va0, bo0);
       c0 += 64 * nch;
     }
-    for (; c0 < nact; c0 += 64) chunk(c0, std::false_type{});
+    for (; c0 < ihi; c0 += 64) chunk(c0, std::false_type{});
+    if (split == nsplit - 1)
+      for (; c0 < nact; c0 += 64) chunk(c0, std::false_type{});
   }
 }
 
@@ -1084,11 +1112,14 @@ static hipError_t launch_apply(hipStream_t st, int nb, const T* V, int64_t vstri
 
 template <typename T, int MODE>
 static hipError_t launch_block_apply(hipStream_t st, const T* V, int64_t vstride, T* B, int64_t bstride,
-                                     const QrShape& s, int P0, int W, int c0, int c1, const T* tbig, T* gout) {
-  const int ncb = (MODE == 2) ? gram_splits(s.nbatch, s.tree_d) : (c1 - c0 + kOuter - 1) / kOuter;
+                                     const QrShape& s, int P0, int W, int c0, int c1, const T* tbig, T* gout,
+                                     int phase = 0, int rsplit = 1, T* wpart = nullptr) {
+  int ncb = (MODE == 2) ? gram_splits(s.nbatch, s.tree_d) : (c1 - c0 + kOuter - 1) / kOuter;
   if (ncb <= 0) return hipSuccess;
+  if (MODE != 2 && phase != 0) ncb *= rsplit;
   hipLaunchKernelGGL((block_apply_kernel<T, MODE>), dim3(ncb, s.nbatch), dim3(kBlkThreads), 0, st, V, vstride, B,
-                     bstride, s.m_full, s.m_last, s.nbatch, s.d, P0, W, s.tree_d, c0, c1, tbig, gout);
+                     bstride, s.m_full, s.m_last, s.nbatch, s.d, P0, W, s.tree_d, c0, c1, tbig, gout, phase, rsplit,
+                     wpart);
   return hipGetLastError();
 }
 
@@ -1099,9 +1130,13 @@ static int n_outer(int d) { return (d + kOuter - 1) / kOuter; }
 // Inner panels are factored and applied inside each outer panel; the outer
 // panel's T_big (kept in tbig for the Q formation) then updates the trailing
 // columns in one pass.
+//
+// With wpart (kRowSplits x 256 W blocks), a trailing update of so few column
+// blocks that they would leave CUs idle runs over kRowSplits row shares: one
+// launch for the shares' partial W = V^T B, one for the update with their sum.
 template <typename T>
 static hipError_t batched_qr(hipStream_t st, T* A, int64_t bstride, const QrShape& s, T* tau, T* tm, T* tbig,
-                             T* gram) {
+                             T* gram, T* wpart = nullptr) {
   const int rpt = pick_rpt(s.m_full > s.m_last ? s.m_full : s.m_last);
   const int64_t t_bstride = (int64_t)s.npanels * s.nb * s.nb;
   for (int o = 0; o < n_outer(s.d); ++o) {
@@ -1124,7 +1159,15 @@ static hipError_t batched_qr(hipStream_t st, T* A, int64_t bstride, const QrShap
     hipLaunchKernelGGL(block_t_kernel<T>, dim3(s.nbatch), dim3(kBlkThreads), 0, st, tm, t_bstride, s.nb, P0, W, gram,
                        gram_splits(s.nbatch, s.tree_d), s.nbatch, tb);
     LR_TRY(hipGetLastError());
-    LR_TRY((launch_block_apply<T, 0>(st, A, bstride, A, bstride, s, P0, W, P0 + W, s.d, tb, nullptr)));
+    const int ncb = (s.d - (P0 + W) + kOuter - 1) / kOuter;
+    if (wpart != nullptr && s.tree_d == 0 && ncb > 0 && ncb * s.nbatch <= 256) {
+      LR_TRY((launch_block_apply<T, 0>(st, A, bstride, A, bstride, s, P0, W, P0 + W, s.d, tb, nullptr, 1, kRowSplits,
+                                       wpart)));
+      LR_TRY((launch_block_apply<T, 0>(st, A, bstride, A, bstride, s, P0, W, P0 + W, s.d, tb, nullptr, 2, kRowSplits,
+                                       wpart)));
+    } else {
+      LR_TRY((launch_block_apply<T, 0>(st, A, bstride, A, bstride, s, P0, W, P0 + W, s.d, tb, nullptr)));
+    }
   }
   return hipSuccess;
 }
@@ -1247,7 +1290,7 @@ static hipError_t tree_run(hipStream_t st, const TreePlan& p, int d, char* base,
 struct TsqrPlan {
   int64_t n;
   int d, leaf_rows, nleaf, m_last;
-  size_t off_work, off_tau, off_t, off_tbig, off_gram;
+  size_t off_work, off_tau, off_t, off_tbig, off_gram, off_wpart;
   TreePlan tree;
   size_t total;
 };
@@ -1273,6 +1316,8 @@ static TsqrPlan make_plan(int64_t n, int d, int leaf_rows) {
   off = align256(off + (size_t)n_outer(d) * p.nleaf * blk * sizeof(T));
   p.off_gram = off;
   off = align256(off + (size_t)kGramSplits * p.nleaf * blk * sizeof(T));
+  p.off_wpart = off;
+  off = align256(off + (size_t)kRowSplits * 256 * blk * sizeof(T));
   p.tree = make_tree_plan(p.nleaf, d, off);
   p.total = p.tree.end;
   return p;
@@ -1298,7 +1343,7 @@ hipError_t tsqr_run(hipStream_t st, int64_t n, int d, int leaf_rows, const T* Y,
 
   // Eq. (1): leaf QRs on a working copy of Y.
   LR_TRY(launch_copy<T>(st, Y, work, n * d));
-  LR_TRY(batched_qr<T>(st, work, lstride, ls, tau, tm, tbig, gram));
+  LR_TRY(batched_qr<T>(st, work, lstride, ls, tau, tm, tbig, gram, reinterpret_cast<T*>(base + p.off_wpart)));
   double* r0 = reinterpret_cast<double*>(base + p.tree.off_r[0]);
   hipLaunchKernelGGL(extract_r_kernel<T>, dim3(ddblocks, p.nleaf), dim3(256), 0, st, work, lstride, d, d, r0,
                      p.nleaf);
